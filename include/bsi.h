@@ -1,0 +1,164 @@
+/*
+ * bsi.h -- B-spline interpolation of periodic spectral fields on MI355X (gfx950).
+ *
+ * The method is the one of van Hinsberg, ten Thije Boonkkamp, Toschi and
+ * Clercx, "On the efficiency and accuracy of interpolation methods for
+ * spectral codes" (SIAM J. Sci. Comput. 2012):
+ *
+ *   prefilter  (Section 7)  multiply every Fourier mode of the field by
+ *              c(kx) c(ky) c(kz) and apply one inverse 3D real FFT, giving the
+ *              B-spline coefficient grid u_B;
+ *   evaluation (Sections 2, 3, 5; Table 1)  for every particle, pick the N^3
+ *              nearest grid points, form the 1D weights M tbar and M^(1) tbar
+ *              per axis, and contract them with the local coefficients to get
+ *              u and all first derivatives.
+ *
+ * Everything is a plain C ABI: device or host pointers and sizes, no
+ * framework types.  All functions return a bsi_status and never throw.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Spectrum   uhat[c][k0][k1][k2], c < ncomp, k0 < n0, k1 < n1, k2 <= n2/2:
+ *            Fourier-series coefficients of a real field on the box
+ *            [0,L0)x[0,L1)x[0,L2), u(x) = sum_k uhat_k exp(2 pi i sum_d k_d x_d / L_d),
+ *            in the real-FFT half-spectrum layout (index k >= n/2+1 of axes
+ *            0 and 1 is the negative wave number k - n).  complex128 or
+ *            complex64, interleaved (re, im).  As for any inverse real FFT,
+ *            only the real parts of the k2 = 0 and k2 = n2/2 entries of the
+ *            transformed lines are used; a Hermitian spectrum is unaffected.
+ * Positions  pos[p][d], FP64, any finite value (wrapped periodically).
+ *            A particle with a non-finite coordinate gets NaN outputs and is
+ *            counted (bsi_field_stats).
+ * Outputs    u[p][c] and grad[p][c][d] = d u_c / d x_d in physical units,
+ *            FP64 for a BSI_F64 coefficient grid, FP32 otherwise.
+ * Streams    every call is asynchronous on the given HIP stream (NULL = the
+ *            context's stream).  Buffers passed in belong to the caller and
+ *            must stay valid until the stream reaches the call's work.
+ *            Faults surface at the next synchronising call as BSI_E_DEVICE.
+ * Threads    a context and its fields are used from one host thread at a time;
+ *            distinct contexts may be used concurrently.
+ * Errors     on failure a thread-local message is available from
+ *            bsi_last_error().
+ */
+#ifndef BSI_H
+#define BSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bsi_status {
+    BSI_OK = 0,
+    BSI_E_INVAL = 1,        /* bad argument (pointer, size, descriptor)              */
+    BSI_E_NOMEM = 2,        /* device or host allocation failed / over budget        */
+    BSI_E_UNSUPPORTED = 3,  /* valid but not implemented (e.g. odd order, n=5*k)     */
+    BSI_E_DEVICE = 4,       /* HIP runtime error or device fault                     */
+    BSI_E_BUSY = 5,         /* server queue full                                     */
+    BSI_E_CANCELLED = 6     /* server request cancelled                              */
+} bsi_status;
+
+/* Storage type of the coefficient grid (and of spectra: F64 = complex128,
+ * F32 = complex64).  BF16 is storage only: evaluation accumulates in FP32. */
+typedef enum bsi_dtype { BSI_F64 = 0, BSI_F32 = 1, BSI_BF16 = 2 } bsi_dtype;
+
+/* Choice of c(k), Section 7.  L2OPT: c = F[B](kappa) / sum_i F[B](kappa+i)^2,
+ * the L2-optimal constants the paper proposes.  INTERP: c = 1 / F_D[B_D](k),
+ * the straightforward inverse of the sampled spline (exact at grid nodes). */
+typedef enum bsi_prefilter { BSI_PREFILTER_L2OPT = 0, BSI_PREFILTER_INTERP = 1 } bsi_prefilter;
+
+typedef struct bsi_field_desc {
+    int32_t n[3];        /* grid points per axis, each 2^a 3^b, 2*order <= n <= 1024   */
+    int32_t ncomp;       /* 1 (scalar) or 3 (vector field, Section 3 last paragraph)   */
+    int32_t order;       /* spline order N (degree N-1): 4 or 6                        */
+    int32_t coef;        /* bsi_dtype of the coefficient grid                          */
+    int32_t prefilter;   /* bsi_prefilter                                              */
+    int32_t reserved;    /* must be 0                                                  */
+    double length[3];    /* box lengths L_d; 0 means 2*pi                              */
+} bsi_field_desc;
+
+/* Evaluation tuning knobs (results never depend on them). */
+typedef struct bsi_eval_config {
+    int32_t sort_tile;   /* cells per Morton tile edge for particle binning; 0 = no binning */
+    int32_t block;       /* threads per workgroup of the gather kernel (64..1024, multiple of 64) */
+    int32_t xcd_remap;   /* 1 = map consecutive binned particle blocks onto one XCD            */
+    int32_t reserved;
+} bsi_eval_config;
+
+typedef struct bsi_ctx bsi_ctx;
+typedef struct bsi_field bsi_field;
+typedef struct bsi_server bsi_server;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t or
+ * NULL) becomes the context's default stream; NULL means the device's null
+ * stream.  The context owns FFT twiddle tables, prefilter tables and scratch. */
+bsi_status bsi_ctx_create(int device, void* hip_stream, bsi_ctx** out);
+/* Destroy a context.  All its fields must have been destroyed. */
+void bsi_ctx_destroy(bsi_ctx* ctx);
+/* Message of the last failure on this host thread ("" if none). */
+const char* bsi_last_error(void);
+/* Library version string. */
+const char* bsi_version(void);
+
+/* ---- fields ------------------------------------------------------------- */
+
+/* Validate `desc` and allocate the field's coefficient grid on the device.
+ * BSI_E_INVAL for bad sizes/ncomp/dtype/lengths, BSI_E_UNSUPPORTED for an
+ * order other than 4 or 6 or an n that is not 2^a 3^b, BSI_E_NOMEM if the
+ * grid does not fit.  The grid is (n0+N-1)(n1+N-1)(n2+N-1)*ncomp elements:
+ * the periodic grid plus N-1 ghost planes per axis, components interleaved. */
+bsi_status bsi_field_create(bsi_ctx* ctx, const bsi_field_desc* desc, bsi_field** out);
+void bsi_field_destroy(bsi_field* field);
+/* Device bytes held by the field (grid and counters). */
+size_t bsi_field_bytes(const bsi_field* field);
+
+/* Prefilter (Section 7): uhat_dev is the device spectrum described above,
+ * complex128 if uhat_prec == BSI_F64 or complex64 if BSI_F32.  The symbol
+ * product is formed and applied in FP64, then one inverse 3D real FFT runs in
+ * FP64 (BSI_F64 grid) or FP32 (BSI_F32 / BSI_BF16 grid; BF16 is a
+ * round-to-nearest-even cast of the FP32 result).  uhat is only read. */
+bsi_status bsi_field_set_spectrum(bsi_field* field, const void* uhat_dev,
+                                  int32_t uhat_prec, void* hip_stream);
+
+/* Load the coefficient grid directly: grid_dev is FP64 [ncomp][n0][n1][n2]
+ * (component-major, no ghosts), cast to the field's storage type.  Lets the
+ * evaluation be checked on a grid computed elsewhere. */
+bsi_status bsi_field_set_coefficients(bsi_field* field, const double* grid_dev,
+                                      void* hip_stream);
+/* Read the coefficient grid back as FP64 [ncomp][n0][n1][n2] (widened from
+ * the storage type). */
+bsi_status bsi_field_get_coefficients(const bsi_field* field, double* grid_dev,
+                                      void* hip_stream);
+
+/* ---- evaluation (Sections 2, 3, 5; Table 1) ----------------------------- */
+
+/* Interpolate u (and grad u if grad_dev != NULL) at P particle positions.
+ * pos_dev: FP64 [P][3]; u_dev: [P][ncomp]; grad_dev: [P][ncomp][3]; device
+ * pointers, 8-byte aligned.  0 <= P < 2^31; P == 0 does nothing. */
+bsi_status bsi_eval(bsi_field* field, const double* pos_dev, int64_t P,
+                    void* u_dev, void* grad_dev, void* hip_stream);
+/* Same with explicit tuning knobs (NULL = the context's tuned defaults). */
+bsi_status bsi_eval_ex(bsi_field* field, const double* pos_dev, int64_t P,
+                       void* u_dev, void* grad_dev, const bsi_eval_config* cfg,
+                       void* hip_stream);
+
+/* Cell index and offset of each particle per axis, exactly as the evaluation
+ * computes them (Section 5 stencil rule): s = x * (n/L) (one FP64 product),
+ * f = floor(s), t = s - f, cell = f mod n in [0, n).  cell_dev: int32 [P][3],
+ * t_dev: FP64 [P][3].  Non-finite coordinates give cell -1, t NaN. */
+bsi_status bsi_debug_cells(bsi_field* field, const double* pos_dev, int64_t P,
+                           int32_t* cell_dev, double* t_dev, void* hip_stream);
+
+/* Number of non-finite positions seen by evaluations of this field so far
+ * (synchronises the field's last stream). */
+bsi_status bsi_field_stats(bsi_field* field, int64_t* nonfinite_positions);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSI_H */

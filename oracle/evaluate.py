@@ -42,17 +42,20 @@ def inv_spacing(n, L):
 def cells(pos, shape, lengths=(TWO_PI, TWO_PI, TWO_PI)):
     """Cell index and offset per particle and axis.
 
-    Returns (cell int64 [P][3], t float64 [P][3], finite bool [P]).  Rows with a
-    non-finite coordinate get cell 0, t 0 and finite=False.
+    Returns (cell int64 [P][3], t float64 [P][3], finite bool [P]).  A particle
+    has no cell when one of its grid coordinates s is not finite (a non-finite
+    position, or a finite one so large that x * n/L overflows); such rows get
+    cell 0, t 0 and finite=False.
     """
     pos = np.asarray(pos, dtype=np.float64)
-    finite = np.isfinite(pos).all(axis=1)
     P = pos.shape[0]
+    with np.errstate(over="ignore", invalid="ignore"):
+        svals = np.stack([pos[:, d] * inv_spacing(shape[d], lengths[d]) for d in range(3)], axis=1)
+    finite = np.isfinite(svals).all(axis=1)
     cell = np.zeros((P, 3), dtype=np.int64)
     t = np.zeros((P, 3), dtype=np.float64)
     for d in range(3):
-        x = np.where(finite, pos[:, d], 0.0)
-        s = x * inv_spacing(shape[d], lengths[d])
+        s = np.where(finite, svals[:, d], 0.0)
         f = np.floor(s)
         t[:, d] = s - f
         r = np.fmod(f, float(shape[d]))          # exact remainder, sign of f

@@ -1,0 +1,182 @@
+"""ctypes binding of libbsi.so: the C ABI of include/bsi.h, one Python function
+per C entry point with the same name.  Argument marshalling only: every step of
+the method runs in the HIP library.  Raises BsiError on a non-OK status.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbsi.so")
+
+BSI_OK = 0
+STATUS_NAMES = {0: "BSI_OK", 1: "BSI_E_INVAL", 2: "BSI_E_NOMEM", 3: "BSI_E_UNSUPPORTED",
+                4: "BSI_E_DEVICE", 5: "BSI_E_BUSY", 6: "BSI_E_CANCELLED"}
+BSI_F64, BSI_F32, BSI_BF16 = 0, 1, 2
+BSI_PREFILTER_L2OPT, BSI_PREFILTER_INTERP = 0, 1
+
+
+class BsiError(RuntimeError):
+    def __init__(self, status, where, msg):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+class FieldDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("ncomp", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("coef", ctypes.c_int32), ("prefilter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("length", ctypes.c_double * 3)]
+
+
+class EvalConfig(ctypes.Structure):
+    _fields_ = [("sort_tile", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class EvalItem(ctypes.Structure):
+    _fields_ = [("field", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("P", ctypes.c_int64),
+                ("u", ctypes.c_void_p), ("grad", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbsi.so; fail loudly if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1201_4060_amd.build`")
+        _lib = ctypes.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+VP = ctypes.c_void_p
+I32 = ctypes.c_int32
+I64 = ctypes.c_int64
+ST = ctypes.c_int
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "bsi_ctx_create": (ST, [ctypes.c_int, VP, ctypes.POINTER(VP)]),
+    "bsi_ctx_destroy": (None, [VP]),
+    "bsi_last_error": (ctypes.c_char_p, []),
+    "bsi_version": (ctypes.c_char_p, []),
+    "bsi_field_create": (ST, [VP, ctypes.POINTER(FieldDesc), ctypes.POINTER(VP)]),
+    "bsi_field_destroy": (None, [VP]),
+    "bsi_field_bytes": (ctypes.c_size_t, [VP]),
+    "bsi_field_set_spectrum": (ST, [VP, VP, I32, VP]),
+    "bsi_field_set_coefficients": (ST, [VP, VP, VP]),
+    "bsi_field_get_coefficients": (ST, [VP, VP, VP]),
+    "bsi_eval": (ST, [VP, VP, I64, VP, VP, VP]),
+    "bsi_eval_ex": (ST, [VP, VP, I64, VP, VP, ctypes.POINTER(EvalConfig), VP]),
+    "bsi_debug_cells": (ST, [VP, VP, I64, VP, VP, VP]),
+    "bsi_field_stats": (ST, [VP, ctypes.POINTER(I64)]),
+}
+
+
+def _declare(L):
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+
+
+def exported_symbols():
+    """Names of SIGNATURES entries the loaded library exports."""
+    L = lib()
+    return [n for n in SIGNATURES if hasattr(L, n)]
+
+
+def _check(status, where):
+    if status != BSI_OK:
+        msg = lib().bsi_last_error()
+        raise BsiError(status, where, msg.decode() if msg else "")
+
+
+def _ptr(x):
+    """Raw address of a torch tensor / int / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+# ---- one function per C entry point ---------------------------------------
+
+def bsi_ctx_create(device=0, stream=None):
+    out = VP()
+    _check(lib().bsi_ctx_create(device, stream, ctypes.byref(out)), "bsi_ctx_create")
+    return out.value
+
+
+def bsi_ctx_destroy(ctx):
+    lib().bsi_ctx_destroy(ctx)
+
+
+def bsi_last_error():
+    v = lib().bsi_last_error()
+    return v.decode() if v else ""
+
+
+def bsi_version():
+    return lib().bsi_version().decode()
+
+
+def make_desc(n, ncomp, order, coef=BSI_F32, prefilter=BSI_PREFILTER_L2OPT, length=(0.0, 0.0, 0.0)):
+    if isinstance(n, int):
+        n = (n, n, n)
+    d = FieldDesc()
+    d.n = (ctypes.c_int32 * 3)(*n)
+    d.ncomp, d.order, d.coef, d.prefilter, d.reserved = ncomp, order, coef, prefilter, 0
+    d.length = (ctypes.c_double * 3)(*length)
+    return d
+
+
+def bsi_field_create(ctx, desc):
+    out = VP()
+    _check(lib().bsi_field_create(ctx, ctypes.byref(desc), ctypes.byref(out)), "bsi_field_create")
+    return out.value
+
+
+def bsi_field_destroy(field):
+    lib().bsi_field_destroy(field)
+
+
+def bsi_field_bytes(field):
+    return lib().bsi_field_bytes(field)
+
+
+def bsi_field_set_spectrum(field, uhat, prec, stream=None):
+    _check(lib().bsi_field_set_spectrum(field, _ptr(uhat), prec, stream), "bsi_field_set_spectrum")
+
+
+def bsi_field_set_coefficients(field, grid, stream=None):
+    _check(lib().bsi_field_set_coefficients(field, _ptr(grid), stream), "bsi_field_set_coefficients")
+
+
+def bsi_field_get_coefficients(field, grid, stream=None):
+    _check(lib().bsi_field_get_coefficients(field, _ptr(grid), stream), "bsi_field_get_coefficients")
+
+
+def bsi_eval(field, pos, P, u, grad=None, stream=None):
+    _check(lib().bsi_eval(field, _ptr(pos), P, _ptr(u), _ptr(grad), stream), "bsi_eval")
+
+
+def bsi_eval_ex(field, pos, P, u, grad=None, cfg=None, stream=None):
+    c = ctypes.byref(cfg) if cfg is not None else None
+    _check(lib().bsi_eval_ex(field, _ptr(pos), P, _ptr(u), _ptr(grad), c, stream), "bsi_eval_ex")
+
+
+def bsi_debug_cells(field, pos, P, cell, t, stream=None):
+    _check(lib().bsi_debug_cells(field, _ptr(pos), P, _ptr(cell), _ptr(t), stream), "bsi_debug_cells")
+
+
+def bsi_field_stats(field):
+    v = I64()
+    _check(lib().bsi_field_stats(field, ctypes.byref(v)), "bsi_field_stats")
+    return v.value

@@ -1,0 +1,110 @@
+"""Thin object wrappers over the C ABI for torch device tensors.
+
+Only marshalling: tensors are passed as raw device pointers and the current
+torch stream as the HIP stream.  Shapes and dtypes are checked here so that a
+wrong tensor fails before it reaches the library.
+"""
+import torch
+
+from . import _bsi
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Context:
+    """bsi_ctx on one HIP device."""
+
+    def __init__(self, device=0, stream=None):
+        self.device = device
+        self.handle = _bsi.bsi_ctx_create(device, stream)
+
+    def close(self):
+        if self.handle:
+            _bsi.bsi_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Field:
+    """bsi_field: a coefficient grid of a scalar or 3-component periodic field."""
+
+    def __init__(self, ctx, n, ncomp, order, coef=_bsi.BSI_F32, prefilter=_bsi.BSI_PREFILTER_L2OPT,
+                 length=(0.0, 0.0, 0.0)):
+        self.ctx = ctx
+        self.n = (n, n, n) if isinstance(n, int) else tuple(n)
+        self.ncomp, self.order, self.coef = ncomp, order, coef
+        self.desc = _bsi.make_desc(self.n, ncomp, order, coef, prefilter, length)
+        self.handle = _bsi.bsi_field_create(ctx.handle, self.desc)
+
+    @property
+    def out_dtype(self):
+        return torch.float64 if self.coef == _bsi.BSI_F64 else torch.float32
+
+    def close(self):
+        if self.handle:
+            _bsi.bsi_field_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def nbytes(self):
+        return _bsi.bsi_field_bytes(self.handle)
+
+    def set_spectrum(self, uhat):
+        """uhat: complex128/complex64 device tensor [ncomp][n0][n1][n2/2+1]."""
+        n0, n1, n2 = self.n
+        assert uhat.is_cuda and uhat.is_contiguous()
+        assert tuple(uhat.shape) == (self.ncomp, n0, n1, n2 // 2 + 1), uhat.shape
+        prec = {torch.complex128: _bsi.BSI_F64, torch.complex64: _bsi.BSI_F32}[uhat.dtype]
+        _bsi.bsi_field_set_spectrum(self.handle, uhat, prec, _stream())
+
+    def set_coefficients(self, grid):
+        """grid: float64 device tensor [ncomp][n0][n1][n2]."""
+        assert grid.is_cuda and grid.is_contiguous() and grid.dtype == torch.float64
+        assert tuple(grid.shape) == (self.ncomp,) + self.n
+        _bsi.bsi_field_set_coefficients(self.handle, grid, _stream())
+
+    def get_coefficients(self):
+        out = torch.empty((self.ncomp,) + self.n, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        _bsi.bsi_field_get_coefficients(self.handle, out, _stream())
+        return out
+
+    def eval(self, pos, grad=True, cfg=None, out=None):
+        """pos: float64 device tensor [P][3] -> (u [P][C], grad [P][C][3] or None)."""
+        assert pos.is_cuda and pos.is_contiguous() and pos.dtype == torch.float64
+        assert pos.dim() == 2 and pos.shape[1] == 3
+        P = pos.shape[0]
+        if out is None:
+            u = torch.empty((P, self.ncomp), dtype=self.out_dtype, device=pos.device)
+            g = torch.empty((P, self.ncomp, 3), dtype=self.out_dtype, device=pos.device) if grad else None
+        else:
+            u, g = out
+        if P == 0:
+            return u, g
+        if cfg is None:
+            _bsi.bsi_eval(self.handle, pos, P, u, g, _stream())
+        else:
+            _bsi.bsi_eval_ex(self.handle, pos, P, u, g, cfg, _stream())
+        return u, g
+
+    def debug_cells(self, pos):
+        P = pos.shape[0]
+        cell = torch.empty((P, 3), dtype=torch.int32, device=pos.device)
+        t = torch.empty((P, 3), dtype=torch.float64, device=pos.device)
+        if P:
+            _bsi.bsi_debug_cells(self.handle, pos, P, cell, t, _stream())
+        return cell, t
+
+    def nonfinite_count(self):
+        return _bsi.bsi_field_stats(self.handle)

@@ -1,0 +1,184 @@
+// Internal declarations of the bsi library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/bsi.h"
+
+namespace bsi {
+
+// ---------------------------------------------------------------- errors ---
+
+void set_error(const std::string& msg);
+void clear_error();
+
+struct Error {
+    bsi_status status;
+    std::string msg;
+};
+
+// Throw-free helper: evaluate a HIP call, on failure record and return.
+#define BSI_HIP(call)                                                            \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            ::bsi::set_error(std::string(#call) + ": " + hipGetErrorString(e_)); \
+            return BSI_E_DEVICE;                                                 \
+        }                                                                        \
+    } while (0)
+
+#define BSI_CHECK(cond, status, msg)   \
+    do {                               \
+        if (!(cond)) {                 \
+            ::bsi::set_error(msg);     \
+            return (status);           \
+        }                              \
+    } while (0)
+
+#define BSI_TRY(expr)                  \
+    do {                               \
+        bsi_status s_ = (expr);        \
+        if (s_ != BSI_OK) return s_;   \
+    } while (0)
+
+// ------------------------------------------------------- small utilities ---
+
+template <typename T>
+struct cplx {
+    T x, y;
+};
+
+inline bool is_2a3b(int n) {
+    if (n <= 0) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+inline size_t dtype_size(int dt) { return dt == BSI_F64 ? 8 : (dt == BSI_F32 ? 4 : 2); }
+
+// ------------------------------------------ B-spline matrix constants -------
+// M_(N)[r][c] (row r = stencil point, column c = power of t) from the general
+// formula of Section 7, evaluated at compile time in integers:
+//   (N-1)! M[r][c] = C(N-1, N-c') * sum_{s=r'}^{N} (-1)^(s-r') C(N, s-r') (N-s)^(N-c')
+// with 1-based r' = r+1, c' = c+1 and 0^0 = 1.  M^(1) = M D (Section 2).
+
+constexpr long long ipow_ll(long long b, int e) {
+    long long r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+constexpr long long binom_ll(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    long long r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+constexpr long long fact_ll(int n) {
+    long long r = 1;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+// (N-1)! * M_(N)[r][c], 0-based
+constexpr long long bspline_numer(int N, int r, int c) {
+    long long acc = 0;
+    for (int s = r + 1; s <= N; ++s) {
+        const int d = s - (r + 1);
+        acc += ((d & 1) ? -1 : 1) * binom_ll(N, d) * ipow_ll(N - s, N - (c + 1));
+    }
+    return binom_ll(N - 1, N - (c + 1)) * acc;
+}
+
+template <int N>
+struct BSpline {
+    double M[N][N];
+    double M1[N][N];
+    constexpr BSpline() : M{}, M1{} {
+        for (int r = 0; r < N; ++r)
+            for (int c = 0; c < N; ++c) {
+                M[r][c] = double(bspline_numer(N, r, c)) / double(fact_ll(N - 1));
+                M1[r][c] = (c + 1 < N)
+                               ? double((c + 1) * bspline_numer(N, r, c + 1)) / double(fact_ll(N - 1))
+                               : 0.0;
+            }
+    }
+};
+
+// B_M(s) at an integer s: the t = 0 column of M_(M) holds the integer samples
+// of the centred B-spline (row j <-> s = M/2 - 1 - j).
+inline double bspline_integer_sample(int M, int s) {
+    const int row = M / 2 - 1 - s;
+    if (row < 0 || row >= M) return 0.0;
+    return double(bspline_numer(M, row, 0)) / double(fact_ll(M - 1));
+}
+
+// ---------------------------------------------------------------- objects ---
+
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace bsi
+
+struct bsi_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cus = 0;
+    size_t lds_per_block = 0;
+    std::mutex mu;
+    // twiddle tables e^{+2 pi i m / len}, m < len, keyed by (len, is_double)
+    std::map<std::pair<int, int>, void*> twiddles;
+    // prefilter constant tables c(k), k < n, FP64, keyed by (n, order, variant, L-bits)
+    std::map<std::tuple<int, int, int>, double*> ctabs;
+    // per-stream scratch, grown on demand
+    std::map<hipStream_t, bsi::Workspace> fft_ws;
+    std::map<hipStream_t, bsi::Workspace> eval_ws;
+    bsi_eval_config tuned{};  // defaults for bsi_eval
+    int live_fields = 0;
+};
+
+struct bsi_field {
+    bsi_ctx* ctx = nullptr;
+    bsi_field_desc desc{};
+    int N = 4;
+    int C = 1;
+    int n[3] = {0, 0, 0};
+    int P[3] = {0, 0, 0};  // padded extents n + N - 1
+    int padlo = 1;         // ghost planes below index 0 (N/2 - 1)
+    double L[3] = {0, 0, 0};
+    double inv_h[3] = {0, 0, 0};
+    void* grid = nullptr;
+    size_t grid_bytes = 0;
+    unsigned long long* counters = nullptr;  // [0] = non-finite positions
+    hipStream_t last_stream = nullptr;
+};
+
+namespace bsi {
+
+hipStream_t pick_stream(bsi_ctx* ctx, void* s);
+bsi_status get_workspace(std::map<hipStream_t, Workspace>& m, hipStream_t s, size_t bytes, void** out);
+bsi_status get_twiddles(bsi_ctx* ctx, int len, bool dbl, const void** out);
+bsi_status get_ctable(bsi_ctx* ctx, int n, int order, int variant, const double** out);
+
+// host-side prefilter constants (symbol.cpp)
+void prefilter_table(int n, int order, int variant, double* out);
+
+// launchers
+bsi_status prefilter_run(bsi_field* f, const void* uhat, int prec, hipStream_t s);
+bsi_status grid_from_dense(bsi_field* f, const double* dense, hipStream_t s);
+bsi_status grid_to_dense(const bsi_field* f, double* dense, hipStream_t s);
+bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
+                    const bsi_eval_config& cfg, hipStream_t s);
+bsi_status debug_cells_run(bsi_field* f, const double* pos, int64_t P, int32_t* cell, double* t,
+                           hipStream_t s);
+
+}  // namespace bsi

@@ -1,0 +1,516 @@
+// Prefilter on the GPU: symbol multiply + one inverse 3D real FFT (Section 7).
+//
+// Pass A  (axis 0)  reads the caller's half spectrum uhat[c][k0][k1][k2],
+//                   multiplies it by c(k0) c(k1) c(k2) in FP64, casts to the
+//                   working precision T and does the inverse complex FFT along
+//                   k0, writing the work buffer (same layout).
+// Pass B  (axis 1)  inverse complex FFT along k1, in place.
+// Pass C  (axis 2)  complex-to-real inverse FFT of each k2 line (length n2/2
+//                   complex FFT after the standard even/odd twist), cast to the
+//                   storage type and written to the ghost-padded, component-
+//                   interleaved coefficient grid.
+//
+// Every line transform is a Stockham autosort FFT held in LDS: each stage has
+// every thread load its radix-R butterflies into registers, apply twiddles
+// from a table of exp(+2 pi i m / len) (computed on the host in FP64), do the
+// radix-R DFT and store to the self-sorted positions.  A workgroup transforms
+// W adjacent lines of a strided axis so that each global row access covers W
+// consecutive elements.
+#include "common.hpp"
+
+namespace bsi {
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul_i(cplx<T> a) { return {-a.y, a.x}; }  // i * a
+
+// Inverse (sign +) DFT of length R in registers.
+template <typename T>
+__device__ __forceinline__ void dft2(cplx<T>* v) {
+    cplx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+template <typename T>
+__device__ __forceinline__ void dft3(cplx<T>* v) {
+    const T h = T(0.86602540378443864676372317075294);  // sin(2 pi / 3)
+    cplx<T> s = cadd(v[1], v[2]);
+    cplx<T> d = csub(v[1], v[2]);
+    cplx<T> m = {v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+    cplx<T> r = {-h * d.y, h * d.x};  // i * h * (v1 - v2)
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+}
+template <typename T>
+__device__ __forceinline__ void dft4(cplx<T>* v) {
+    cplx<T> s0 = cadd(v[0], v[2]), s1 = csub(v[0], v[2]);
+    cplx<T> s2 = cadd(v[1], v[3]), s3 = cmul_i(csub(v[1], v[3]));
+    v[0] = cadd(s0, s2);
+    v[2] = csub(s0, s2);
+    v[1] = cadd(s1, s3);
+    v[3] = csub(s1, s3);
+}
+template <typename T>
+__device__ __forceinline__ void dft8(cplx<T>* v) {
+    const T r2 = T(0.70710678118654752440084436210485);
+    cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4(e);
+    dft4(o);
+    o[1] = {r2 * (o[1].x - o[1].y), r2 * (o[1].x + o[1].y)};    // * e^{+i pi/4}
+    o[2] = cmul_i(o[2]);                                         // * e^{+i pi/2}
+    o[3] = {-r2 * (o[3].x + o[3].y), r2 * (o[3].x - o[3].y)};   // * e^{+3i pi/4}
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[q] = cadd(e[q], o[q]);
+        v[q + 4] = csub(e[q], o[q]);
+    }
+}
+template <typename T, int R>
+__device__ __forceinline__ void dft(cplx<T>* v) {
+    if constexpr (R == 2) dft2(v);
+    else if constexpr (R == 3) dft3(v);
+    else if constexpr (R == 4) dft4(v);
+    else dft8(v);
+}
+
+template <int REM>
+struct Radix {
+    static constexpr int value = (REM % 3 == 0) ? 3 : (REM % 8 == 0) ? 8 : (REM % 4 == 0) ? 4 : 2;
+};
+
+// Stockham stages NS.. of an inverse FFT of length LEN on one LDS line.
+// tw[m * TWS] = exp(+2 pi i m / LEN).  All threads of the block must call this
+// with the same template arguments (it contains block barriers).
+template <typename T, int LEN, int TEAM, int NS, int TWS>
+__device__ __forceinline__ void fft_stages(cplx<T>* buf, const cplx<T>* tw, int lane) {
+    if constexpr (NS < LEN) {
+        constexpr int R = Radix<LEN / NS>::value;
+        constexpr int NB = LEN / R;
+        constexpr int PER = (NB + TEAM - 1) / TEAM;
+        constexpr int TSTEP = LEN / (NS * R);
+        cplx<T> v[PER][R];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int j = lane + q * TEAM;
+            if (PER * TEAM == NB || j < NB) {
+                const int k = j % NS;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[q][r] = buf[j + r * NB];
+                if constexpr (NS > 1) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[r * k * TSTEP * TWS]);
+                }
+                dft<T, R>(v[q]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int j = lane + q * TEAM;
+            if (PER * TEAM == NB || j < NB) {
+                const int k = j % NS;
+                const int base = (j / NS) * NS * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[base + r * NS] = v[q][r];
+            }
+        }
+        __syncthreads();
+        fft_stages<T, LEN, TEAM, NS * R, TWS>(buf, tw, lane);
+    }
+}
+
+// Lines per workgroup for the strided passes: keep the LDS line block near 33 KB.
+template <typename T, int LEN>
+struct StridedCfg {
+    static constexpr int bytes = int(sizeof(cplx<T>));
+    static constexpr int raw = (33 * 1024) / ((LEN + 1) * bytes);
+    static constexpr int W = raw >= 16 ? 16 : raw >= 8 ? 8 : raw >= 4 ? 4 : 2;
+    static constexpr int THREADS = 256;
+    static constexpr int TEAM = THREADS / W;
+};
+
+// Passes A and B.  Element (c, a, other, k2) of the [C][..][..][H] array sits
+// at c*sComp + a*sAxis + other*sOther + k2; the FFT runs along a.
+// FIRST: input is the caller's spectrum (InT pairs), multiplied by the FP64
+// symbol cAxis[a] * cOther[other] * c2[k2]; otherwise in-place on the work
+// buffer (in == out).
+template <typename T, typename InT, int LEN, bool FIRST>
+__global__ __launch_bounds__(256) void k_fft_axis(const InT* in, cplx<T>* out, int H, long sAxis,
+                                                  long sOther, long sComp, const double* cAxis,
+                                                  const double* cOther, const double* c2,
+                                                  const cplx<T>* twg) {
+    using Cfg = StridedCfg<T, LEN>;
+    constexpr int W = Cfg::W;
+    constexpr int LP = LEN + 1;
+    __shared__ cplx<T> lines[W * LP];
+    __shared__ cplx<T> tw[LEN];
+    const int tid = threadIdx.x;
+    const int k2_0 = blockIdx.x * W;
+    const int other = blockIdx.y;
+    const long base = long(blockIdx.z) * sComp + long(other) * sOther + k2_0;
+
+    for (int i = tid; i < LEN; i += Cfg::THREADS) tw[i] = twg[i];
+    double cO = 1.0;
+    if constexpr (FIRST) cO = cOther[other];
+    for (int idx = tid; idx < LEN * W; idx += Cfg::THREADS) {
+        const int a = idx / W, w = idx % W;
+        cplx<T> v = {T(0), T(0)};
+        if (k2_0 + w < H) {
+            const long e = base + long(a) * sAxis + w;
+            if constexpr (FIRST) {
+                const double re = double(in[2 * e]);
+                const double im = double(in[2 * e + 1]);
+                const double m = (cAxis[a] * cO) * c2[k2_0 + w];
+                v = {T(re * m), T(im * m)};
+            } else {
+                v = reinterpret_cast<const cplx<T>*>(in)[e];
+            }
+        }
+        lines[w * LP + a] = v;
+    }
+    __syncthreads();
+    fft_stages<T, LEN, Cfg::TEAM, 1, 1>(lines + (tid / Cfg::TEAM) * LP, tw, tid % Cfg::TEAM);
+    for (int idx = tid; idx < LEN * W; idx += Cfg::THREADS) {
+        const int a = idx / W, w = idx % W;
+        if (k2_0 + w < H) out[base + long(a) * sAxis + w] = lines[w * LP + a];
+    }
+}
+
+// ---- storage conversions -------------------------------------------------
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    // IEEE binary32 -> bfloat16, round to nearest, ties to even; NaN stays NaN.
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+template <typename O, typename T>
+__device__ __forceinline__ O store_cast(T v) {
+    if constexpr (sizeof(O) == 2) return f32_to_bf16_rne(float(v));
+    else return O(v);
+}
+template <typename O>
+__device__ __forceinline__ double load_widen(O v) {
+    if constexpr (sizeof(O) == 2) return double(__uint_as_float(uint32_t(v) << 16));
+    else return double(v);
+}
+
+// Pass C configuration: TEAM threads per length-M transform, LINES grid rows of
+// C components per workgroup.
+template <typename T, int M, int C>
+struct C2rCfg {
+    static constexpr int TEAM = M >= 512 ? 64 : M >= 256 ? 32 : M >= 128 ? 16 : 8;
+    static constexpr int LINES0 = 256 / (C * TEAM);
+    // keep the LDS rows (plus the 2M twiddles) within about 40 KB
+    static constexpr int LBYTES = (40 * 1024 - 2 * M * int(sizeof(cplx<T>))) / (C * (M + 2) * int(sizeof(cplx<T>)));
+    static constexpr int LINES1 = LINES0 < LBYTES ? LINES0 : LBYTES;
+    static constexpr int LINES = LINES1 < 1 ? 1 : LINES1;
+    static constexpr int THREADS = LINES * C * TEAM;
+};
+
+// Pass C.  work[c][g0][g1][k2] (k2 <= M) -> grid[p0][p1][p2][c] with ghost
+// planes: padded index p holds grid index (p - padlo) mod n on every axis.
+// tw[m] = exp(+2 pi i m / (2M)), m < 2M.
+template <typename T, typename OutT, int M, int C>
+__global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, OutT* __restrict__ grid,
+                                             int n0, int n1, int P0, int P1, int P2, int padlo,
+                                             const cplx<T>* __restrict__ twg) {
+    using Cfg = C2rCfg<T, M, C>;
+    constexpr int H = M + 1;
+    constexpr int LP = M + 2;
+    constexpr int NL = Cfg::LINES * C;  // transforms per block
+    __shared__ cplx<T> zb[NL * LP];
+    __shared__ cplx<T> tw[2 * M];
+    const int tid = threadIdx.x;
+    const long nlines = long(n0) * n1;
+    const long line0 = long(blockIdx.x) * Cfg::LINES;
+    const long compStride = nlines * H;
+
+    for (int i = tid; i < 2 * M; i += Cfg::THREADS) tw[i] = twg[i];
+    // load every (line, component) row of H complex values
+    for (int idx = tid; idx < NL * H; idx += Cfg::THREADS) {
+        const int f = idx / H, k = idx % H;
+        const int l = f / C, c = f % C;
+        cplx<T> v = {T(0), T(0)};
+        if (line0 + l < nlines) v = work[long(c) * compStride + (line0 + l) * H + k];
+        zb[f * LP + k] = v;
+    }
+    __syncthreads();
+    // even/odd twist: Z[k] = (X[k] + conj X[M-k]) + i e^{2 pi i k/(2M)} (X[k] - conj X[M-k]),
+    // with the imaginary parts of X[0] and X[M] dropped (real-FFT semantics).
+    for (int idx = tid; idx < NL * (M / 2 + 1); idx += Cfg::THREADS) {
+        const int f = idx / (M / 2 + 1), k = idx % (M / 2 + 1);
+        cplx<T>* X = zb + f * LP;
+        if (k == 0) {
+            const T a = X[0].x, b = X[M].x;
+            X[0] = {a + b, a - b};
+        } else {
+            const int kk = M - k;
+            const cplx<T> A = X[k], B = X[kk];
+            const cplx<T> Bc = {B.x, -B.y}, Ac = {A.x, -A.y};
+            const cplx<T> z1 = cadd(cadd(A, Bc), cmul_i(cmul(tw[k], csub(A, Bc))));
+            if (k < kk) {
+                const cplx<T> z2 = cadd(cadd(B, Ac), cmul_i(cmul(tw[kk], csub(B, Ac))));
+                X[kk] = z2;
+            }
+            X[k] = z1;
+        }
+    }
+    __syncthreads();
+    fft_stages<T, M, Cfg::TEAM, 1, 2>(zb + (tid / Cfg::TEAM) * LP, tw, tid % Cfg::TEAM);
+    // scatter rows (with periodic ghost copies) to the interleaved grid
+    const int rowElems = P2 * C;
+    for (int l = 0; l < Cfg::LINES; ++l) {
+        const long line = line0 + l;
+        if (line >= nlines) break;
+        const int g0 = int(line / n1), g1 = int(line % n1);
+        // padded rows holding grid row g: g + padlo, and one periodic ghost copy
+        // (g + padlo - n or g + padlo + n) when that falls inside [0, P)
+        const int p0a = g0 + padlo;
+        const int p0b = (p0a - n0 >= 0) ? p0a - n0 : ((p0a + n0 < P0) ? p0a + n0 : -1);
+        const int p1a = g1 + padlo;
+        const int p1b = (p1a - n1 >= 0) ? p1a - n1 : ((p1a + n1 < P1) ? p1a + n1 : -1);
+        OutT* r_aa = grid + (long(p0a) * P1 + p1a) * rowElems;
+        OutT* r_ab = p1b >= 0 ? grid + (long(p0a) * P1 + p1b) * rowElems : nullptr;
+        OutT* r_ba = p0b >= 0 ? grid + (long(p0b) * P1 + p1a) * rowElems : nullptr;
+        OutT* r_bb = (p0b >= 0 && p1b >= 0) ? grid + (long(p0b) * P1 + p1b) * rowElems : nullptr;
+        for (int e = tid; e < rowElems; e += Cfg::THREADS) {
+            const int p2 = e / C, c = e % C;
+            int g2 = p2 - padlo;
+            if (g2 < 0) g2 += 2 * M;
+            else if (g2 >= 2 * M) g2 -= 2 * M;
+            const cplx<T> z = zb[(l * C + c) * LP + (g2 >> 1)];
+            const OutT v = store_cast<OutT>((g2 & 1) ? z.y : z.x);
+            r_aa[e] = v;
+            if (r_ab) r_ab[e] = v;
+            if (r_ba) r_ba[e] = v;
+            if (r_bb) r_bb[e] = v;
+        }
+    }
+}
+
+// Dense FP64 [C][n0][n1][n2] <-> padded interleaved grid.
+template <typename O>
+__global__ void k_from_dense(const double* __restrict__ dense, O* __restrict__ grid, int C, int n0,
+                             int n1, int n2, int P0, int P1, int P2, int padlo) {
+    const long total = long(P0) * P1 * P2 * C;
+    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < total;
+         i += long(gridDim.x) * blockDim.x) {
+        const int c = int(i % C);
+        long r = i / C;
+        const int p2 = int(r % P2);
+        r /= P2;
+        const int p1 = int(r % P1);
+        const int p0 = int(r / P1);
+        int g0 = p0 - padlo, g1 = p1 - padlo, g2 = p2 - padlo;
+        g0 += (g0 < 0) ? n0 : (g0 >= n0 ? -n0 : 0);
+        g1 += (g1 < 0) ? n1 : (g1 >= n1 ? -n1 : 0);
+        g2 += (g2 < 0) ? n2 : (g2 >= n2 ? -n2 : 0);
+        grid[i] = store_cast<O>(dense[((long(c) * n0 + g0) * n1 + g1) * n2 + g2]);
+    }
+}
+template <typename O>
+__global__ void k_to_dense(const O* __restrict__ grid, double* __restrict__ dense, int C, int n0,
+                           int n1, int n2, int P1, int P2, int padlo) {
+    const long total = long(C) * n0 * n1 * n2;
+    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < total;
+         i += long(gridDim.x) * blockDim.x) {
+        long r = i;
+        const int g2 = int(r % n2);
+        r /= n2;
+        const int g1 = int(r % n1);
+        r /= n1;
+        const int g0 = int(r % n0);
+        const int c = int(r / n0);
+        dense[i] = load_widen<O>(grid[((long(g0 + padlo) * P1 + (g1 + padlo)) * P2 + (g2 + padlo)) * C + c]);
+    }
+}
+
+// ------------------------------------------------------------- launchers ---
+
+namespace {
+
+template <typename T, typename InT, bool FIRST>
+bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, long sAxis, long sOther,
+                       long sComp, const double* cAxis, const double* cOther, const double* c2,
+                       const cplx<T>* tw, hipStream_t s, int* Wout) {
+#define BSI_AXIS_CASE(L)                                                                           \
+    case L: {                                                                                      \
+        *Wout = StridedCfg<T, L>::W;                                                               \
+        grid.x = (H + StridedCfg<T, L>::W - 1) / StridedCfg<T, L>::W;                              \
+        hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), grid, dim3(256), 0, s, in, out, H, sAxis, \
+                           sOther, sComp, cAxis, cOther, c2, tw);                                  \
+        break;                                                                                     \
+    }
+    switch (len) {
+        BSI_AXIS_CASE(8)
+        BSI_AXIS_CASE(12)
+        BSI_AXIS_CASE(16)
+        BSI_AXIS_CASE(24)
+        BSI_AXIS_CASE(32)
+        BSI_AXIS_CASE(48)
+        BSI_AXIS_CASE(64)
+        BSI_AXIS_CASE(96)
+        BSI_AXIS_CASE(128)
+        BSI_AXIS_CASE(192)
+        BSI_AXIS_CASE(256)
+        BSI_AXIS_CASE(384)
+        BSI_AXIS_CASE(512)
+        BSI_AXIS_CASE(768)
+        BSI_AXIS_CASE(1024)
+        default:
+            set_error("unsupported FFT length " + std::to_string(len));
+            return BSI_E_UNSUPPORTED;
+    }
+#undef BSI_AXIS_CASE
+    BSI_HIP(hipGetLastError());
+    return BSI_OK;
+}
+
+template <typename T, typename OutT, int C>
+bsi_status launch_c2r(int M, const cplx<T>* work, OutT* grid, int n0, int n1, int P0, int P1, int P2,
+                      int padlo, const cplx<T>* tw, hipStream_t s) {
+    const long nlines = long(n0) * n1;
+#define BSI_C2R_CASE(MM)                                                                           \
+    case MM: {                                                                                     \
+        using Cfg = C2rCfg<T, MM, C>;                                                                 \
+        const unsigned nb = unsigned((nlines + Cfg::LINES - 1) / Cfg::LINES);                      \
+        hipLaunchKernelGGL((k_c2r<T, OutT, MM, C>), dim3(nb), dim3(Cfg::THREADS), 0, s, work, grid, \
+                           n0, n1, P0, P1, P2, padlo, tw);                                         \
+        break;                                                                                     \
+    }
+    switch (M) {
+        BSI_C2R_CASE(4)
+        BSI_C2R_CASE(6)
+        BSI_C2R_CASE(8)
+        BSI_C2R_CASE(12)
+        BSI_C2R_CASE(16)
+        BSI_C2R_CASE(24)
+        BSI_C2R_CASE(32)
+        BSI_C2R_CASE(48)
+        BSI_C2R_CASE(64)
+        BSI_C2R_CASE(96)
+        BSI_C2R_CASE(128)
+        BSI_C2R_CASE(192)
+        BSI_C2R_CASE(256)
+        BSI_C2R_CASE(384)
+        BSI_C2R_CASE(512)
+        default:
+            set_error("unsupported real FFT length " + std::to_string(2 * M));
+            return BSI_E_UNSUPPORTED;
+    }
+#undef BSI_C2R_CASE
+    BSI_HIP(hipGetLastError());
+    return BSI_OK;
+}
+
+template <typename T, typename InT, typename OutT>
+bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_t s) {
+    bsi_ctx* ctx = f->ctx;
+    const int n0 = f->n[0], n1 = f->n[1], n2 = f->n[2], C = f->C;
+    const int H = n2 / 2 + 1;
+    const size_t elems = size_t(C) * n0 * n1 * H;
+    void* wsp = nullptr;
+    BSI_TRY(get_workspace(ctx->fft_ws, s, elems * sizeof(cplx<T>), &wsp));
+    cplx<T>* work = static_cast<cplx<T>*>(wsp);
+    const double *c0, *c1, *c2;
+    BSI_TRY(get_ctable(ctx, n0, f->N, f->desc.prefilter, &c0));
+    BSI_TRY(get_ctable(ctx, n1, f->N, f->desc.prefilter, &c1));
+    BSI_TRY(get_ctable(ctx, n2, f->N, f->desc.prefilter, &c2));
+    const void *tw0, *tw1, *tw2;
+    const bool dbl = sizeof(T) == 8;
+    BSI_TRY(get_twiddles(ctx, n0, dbl, &tw0));
+    BSI_TRY(get_twiddles(ctx, n1, dbl, &tw1));
+    BSI_TRY(get_twiddles(ctx, n2, dbl, &tw2));
+    const long sComp = long(n0) * n1 * H;
+    int W = 0;
+    // pass A: axis 0 (stride n1*H), other = k1 (stride H)
+    BSI_TRY((launch_axis<T, InT, true>(n0, dim3(1, n1, C), uhat, work, H, long(n1) * H, long(H), sComp,
+                                       c0, c1, c2, static_cast<const cplx<T>*>(tw0), s, &W)));
+    // pass B: axis 1 (stride H), other = k0 (stride n1*H), in place
+    BSI_TRY((launch_axis<T, T, false>(n1, dim3(1, n0, C), reinterpret_cast<const T*>(work), work, H,
+                                      long(H), long(n1) * H, sComp, nullptr, nullptr, nullptr,
+                                      static_cast<const cplx<T>*>(tw1), s, &W)));
+    // pass C: c2r along axis 2
+    const int M = n2 / 2;
+    if (C == 1)
+        return launch_c2r<T, OutT, 1>(M, work, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->padlo,
+                                      static_cast<const cplx<T>*>(tw2), s);
+    return launch_c2r<T, OutT, 3>(M, work, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->padlo,
+                                  static_cast<const cplx<T>*>(tw2), s);
+}
+
+}  // namespace
+
+bsi_status prefilter_run(bsi_field* f, const void* uhat, int prec, hipStream_t s) {
+    const int coef = f->desc.coef;
+    if (coef == BSI_F64) {
+        if (prec == BSI_F64)
+            return prefilter_typed<double, double, double>(f, static_cast<const double*>(uhat),
+                                                           static_cast<double*>(f->grid), s);
+        return prefilter_typed<double, float, double>(f, static_cast<const float*>(uhat),
+                                                      static_cast<double*>(f->grid), s);
+    }
+    if (coef == BSI_F32) {
+        if (prec == BSI_F64)
+            return prefilter_typed<float, double, float>(f, static_cast<const double*>(uhat),
+                                                         static_cast<float*>(f->grid), s);
+        return prefilter_typed<float, float, float>(f, static_cast<const float*>(uhat),
+                                                    static_cast<float*>(f->grid), s);
+    }
+    if (prec == BSI_F64)
+        return prefilter_typed<float, double, uint16_t>(f, static_cast<const double*>(uhat),
+                                                        static_cast<uint16_t*>(f->grid), s);
+    return prefilter_typed<float, float, uint16_t>(f, static_cast<const float*>(uhat),
+                                                   static_cast<uint16_t*>(f->grid), s);
+}
+
+bsi_status grid_from_dense(bsi_field* f, const double* dense, hipStream_t s) {
+    const long total = long(f->P[0]) * f->P[1] * f->P[2] * f->C;
+    const unsigned nb = unsigned(std::min<long>((total + 255) / 256, 65535L * 8));
+    if (f->desc.coef == BSI_F64)
+        hipLaunchKernelGGL(k_from_dense<double>, dim3(nb), dim3(256), 0, s, dense,
+                           static_cast<double*>(f->grid), f->C, f->n[0], f->n[1], f->n[2], f->P[0],
+                           f->P[1], f->P[2], f->padlo);
+    else if (f->desc.coef == BSI_F32)
+        hipLaunchKernelGGL(k_from_dense<float>, dim3(nb), dim3(256), 0, s, dense,
+                           static_cast<float*>(f->grid), f->C, f->n[0], f->n[1], f->n[2], f->P[0],
+                           f->P[1], f->P[2], f->padlo);
+    else
+        hipLaunchKernelGGL(k_from_dense<uint16_t>, dim3(nb), dim3(256), 0, s, dense,
+                           static_cast<uint16_t*>(f->grid), f->C, f->n[0], f->n[1], f->n[2], f->P[0],
+                           f->P[1], f->P[2], f->padlo);
+    BSI_HIP(hipGetLastError());
+    return BSI_OK;
+}
+
+bsi_status grid_to_dense(const bsi_field* f, double* dense, hipStream_t s) {
+    const long total = long(f->C) * f->n[0] * f->n[1] * f->n[2];
+    const unsigned nb = unsigned(std::min<long>((total + 255) / 256, 65535L * 8));
+    if (f->desc.coef == BSI_F64)
+        hipLaunchKernelGGL(k_to_dense<double>, dim3(nb), dim3(256), 0, s,
+                           static_cast<const double*>(f->grid), dense, f->C, f->n[0], f->n[1], f->n[2],
+                           f->P[1], f->P[2], f->padlo);
+    else if (f->desc.coef == BSI_F32)
+        hipLaunchKernelGGL(k_to_dense<float>, dim3(nb), dim3(256), 0, s,
+                           static_cast<const float*>(f->grid), dense, f->C, f->n[0], f->n[1], f->n[2],
+                           f->P[1], f->P[2], f->padlo);
+    else
+        hipLaunchKernelGGL(k_to_dense<uint16_t>, dim3(nb), dim3(256), 0, s,
+                           static_cast<const uint16_t*>(f->grid), dense, f->C, f->n[0], f->n[1],
+                           f->n[2], f->P[1], f->P[2], f->padlo);
+    BSI_HIP(hipGetLastError());
+    return BSI_OK;
+}
+
+}  // namespace bsi
