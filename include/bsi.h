@@ -84,7 +84,9 @@ typedef struct bsi_eval_config {
     int32_t sort_tile;   /* cells per Morton tile edge for particle binning; 0 = no binning */
     int32_t block;       /* threads per workgroup of the gather kernel (64..1024, multiple of 64) */
     int32_t xcd_remap;   /* 1 = map consecutive binned particle blocks onto one XCD            */
-    int32_t reserved;
+    int32_t variant;     /* 0 = LDS-tiled gather when sort_tile > 0 (one workgroup per Morton
+                            tile, tile sizes 4, 6, 8, 10, 12, 16 within 64 KB of LDS);
+                            1 = one thread per particle reading the grid directly */
 } bsi_eval_config;
 
 typedef struct bsi_ctx bsi_ctx;
@@ -156,6 +158,20 @@ bsi_status bsi_debug_cells(bsi_field* field, const double* pos_dev, int64_t P,
 /* Number of non-finite positions seen by evaluations of this field so far
  * (synchronises the field's last stream). */
 bsi_status bsi_field_stats(bsi_field* field, int64_t* nonfinite_positions);
+
+/* ---- stage timing -------------------------------------------------------- */
+
+/* Enable (1) or disable (0) per-stage timing on a context.  While enabled, the
+ * library brackets each of its kernel launches with HIP events recorded on the
+ * launch stream, so durations are those of the kernels themselves.  Stages:
+ * "fft_axis0", "fft_axis1", "fft_c2r", "bin_count", "bin_scan", "bin_scatter",
+ * "gather", "batch_gather". */
+bsi_status bsi_ctx_set_timing(bsi_ctx* ctx, int32_t enabled);
+/* Total milliseconds and number of launches recorded for `stage` since the
+ * last reset (waits for the recorded events). */
+bsi_status bsi_ctx_read_timing(bsi_ctx* ctx, const char* stage, double* total_ms, int64_t* launches);
+/* Forget all recorded timings. */
+bsi_status bsi_ctx_reset_timing(bsi_ctx* ctx);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,7 @@ class FieldDesc(ctypes.Structure):
 
 class EvalConfig(ctypes.Structure):
     _fields_ = [("sort_tile", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("xcd_remap", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class EvalItem(ctypes.Structure):
@@ -73,6 +73,10 @@ SIGNATURES = {
     "bsi_eval_ex": (ST, [VP, VP, I64, VP, VP, ctypes.POINTER(EvalConfig), VP]),
     "bsi_debug_cells": (ST, [VP, VP, I64, VP, VP, VP]),
     "bsi_field_stats": (ST, [VP, ctypes.POINTER(I64)]),
+    "bsi_ctx_set_timing": (ST, [VP, I32]),
+    "bsi_ctx_read_timing": (ST, [VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(I64)]),
+    "bsi_ctx_reset_timing": (ST, [VP]),
 }
 
 
@@ -180,3 +184,19 @@ def bsi_field_stats(field):
     v = I64()
     _check(lib().bsi_field_stats(field, ctypes.byref(v)), "bsi_field_stats")
     return v.value
+
+
+def bsi_ctx_set_timing(ctx, enabled):
+    _check(lib().bsi_ctx_set_timing(ctx, 1 if enabled else 0), "bsi_ctx_set_timing")
+
+
+def bsi_ctx_read_timing(ctx, stage):
+    ms = ctypes.c_double()
+    n = I64()
+    _check(lib().bsi_ctx_read_timing(ctx, stage.encode(), ctypes.byref(ms), ctypes.byref(n)),
+           "bsi_ctx_read_timing")
+    return ms.value, n.value
+
+
+def bsi_ctx_reset_timing(ctx):
+    _check(lib().bsi_ctx_reset_timing(ctx), "bsi_ctx_reset_timing")

@@ -15,6 +15,63 @@ thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 
+StageTimer::StageTimer(bsi_ctx* ctx, const char* stage, hipStream_t s) : ctx_(ctx), stage_(stage), s_(s) {
+    if (!ctx_ || !ctx_->timing) return;
+    std::lock_guard<std::mutex> lk(ctx_->mu);
+    if (!ctx_->event_pool.empty()) {
+        start_ = ctx_->event_pool.back();
+        ctx_->event_pool.pop_back();
+    } else if (hipEventCreate(&start_) != hipSuccess) {
+        (void)hipGetLastError();
+        start_ = nullptr;
+        return;
+    }
+    if (hipEventRecord(start_, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx_->event_pool.push_back(start_);
+        start_ = nullptr;
+    }
+}
+
+StageTimer::~StageTimer() {
+    if (!start_) return;
+    std::lock_guard<std::mutex> lk(ctx_->mu);
+    hipEvent_t stop = nullptr;
+    if (!ctx_->event_pool.empty()) {
+        stop = ctx_->event_pool.back();
+        ctx_->event_pool.pop_back();
+    } else if (hipEventCreate(&stop) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx_->event_pool.push_back(start_);
+        return;
+    }
+    if (hipEventRecord(stop, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx_->event_pool.push_back(start_);
+        ctx_->event_pool.push_back(stop);
+        return;
+    }
+    ctx_->pending.push_back({std::string(stage_), start_, stop});
+}
+
+namespace {
+// Resolve recorded event pairs into per-stage totals (caller holds ctx->mu).
+bsi_status drain_timing(bsi_ctx* ctx) {
+    for (auto& p : ctx->pending) {
+        float ms = 0.f;
+        BSI_HIP(hipEventSynchronize(p.stop));
+        BSI_HIP(hipEventElapsedTime(&ms, p.start, p.stop));
+        auto& tot = ctx->stage_totals[p.stage];
+        tot.first += double(ms);
+        tot.second += 1;
+        ctx->event_pool.push_back(p.start);
+        ctx->event_pool.push_back(p.stop);
+    }
+    ctx->pending.clear();
+    return BSI_OK;
+}
+}  // namespace
+
 hipStream_t pick_stream(bsi_ctx* ctx, void* s) {
     return s ? static_cast<hipStream_t>(s) : ctx->stream;
 }
@@ -153,10 +210,44 @@ bsi_status bsi_ctx_create(int device, void* hip_stream, bsi_ctx** out) {
     return BSI_OK;
 }
 
+bsi_status bsi_ctx_set_timing(bsi_ctx* ctx, int32_t enabled) {
+    clear_error();
+    BSI_CHECK(ctx != nullptr, BSI_E_INVAL, "ctx is NULL");
+    ctx->timing = enabled != 0;
+    return BSI_OK;
+}
+
+bsi_status bsi_ctx_read_timing(bsi_ctx* ctx, const char* stage, double* total_ms, int64_t* launches) {
+    clear_error();
+    BSI_CHECK(ctx && stage && total_ms && launches, BSI_E_INVAL, "NULL argument");
+    BSI_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    BSI_TRY(drain_timing(ctx));
+    auto it = ctx->stage_totals.find(stage);
+    *total_ms = it == ctx->stage_totals.end() ? 0.0 : it->second.first;
+    *launches = it == ctx->stage_totals.end() ? 0 : it->second.second;
+    return BSI_OK;
+}
+
+bsi_status bsi_ctx_reset_timing(bsi_ctx* ctx) {
+    clear_error();
+    BSI_CHECK(ctx != nullptr, BSI_E_INVAL, "ctx is NULL");
+    BSI_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    BSI_TRY(drain_timing(ctx));
+    ctx->stage_totals.clear();
+    return BSI_OK;
+}
+
 void bsi_ctx_destroy(bsi_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    for (auto& p : ctx->pending) {
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
+    }
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     for (auto& kv : ctx->twiddles) (void)hipFree(kv.second);
     for (auto& kv : ctx->ctabs) (void)hipFree(kv.second);
     for (auto& kv : ctx->fft_ws) (void)hipFree(kv.second.ptr);

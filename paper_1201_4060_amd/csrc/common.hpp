@@ -144,6 +144,15 @@ struct bsi_ctx {
     std::map<hipStream_t, bsi::Workspace> eval_ws;
     bsi_eval_config tuned{};  // defaults for bsi_eval
     int live_fields = 0;
+    // stage timing (hipEvent pairs recorded around kernel launches)
+    bool timing = false;
+    struct Pending {
+        std::string stage;
+        hipEvent_t start, stop;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::map<std::string, std::pair<double, int64_t>> stage_totals;
 };
 
 struct bsi_field {
@@ -163,6 +172,21 @@ struct bsi_field {
 };
 
 namespace bsi {
+
+// Brackets the kernel launches of one stage with events when timing is on.
+class StageTimer {
+   public:
+    StageTimer(bsi_ctx* ctx, const char* stage, hipStream_t s);
+    ~StageTimer();
+    StageTimer(const StageTimer&) = delete;
+    StageTimer& operator=(const StageTimer&) = delete;
+
+   private:
+    bsi_ctx* ctx_;
+    const char* stage_;
+    hipStream_t s_;
+    hipEvent_t start_ = nullptr;
+};
 
 hipStream_t pick_stream(bsi_ctx* ctx, void* s);
 bsi_status get_workspace(std::map<hipStream_t, Workspace>& m, hipStream_t s, size_t bytes, void** out);

@@ -129,13 +129,16 @@ __device__ __forceinline__ void fft_stages(cplx<T>* buf, const cplx<T>* tw, int 
 }
 
 // Lines per workgroup for the strided passes: keep the LDS line block near 33 KB.
+// W lines per workgroup, TEAM threads per line; TEAM divides LEN so that each
+// thread moves a fixed line and a fixed set of rows.
 template <typename T, int LEN>
 struct StridedCfg {
     static constexpr int bytes = int(sizeof(cplx<T>));
     static constexpr int raw = (33 * 1024) / ((LEN + 1) * bytes);
     static constexpr int W = raw >= 16 ? 16 : raw >= 8 ? 8 : raw >= 4 ? 4 : 2;
-    static constexpr int THREADS = 256;
-    static constexpr int TEAM = THREADS / W;
+    static constexpr int POW2 = LEN & (-LEN);  // largest power of two dividing LEN
+    static constexpr int TEAM = (256 / W) < POW2 ? (256 / W) : POW2;
+    static constexpr int THREADS = W * TEAM;
 };
 
 // Passes A and B.  Element (c, a, other, k2) of the [C][..][..][H] array sits
@@ -159,29 +162,47 @@ __global__ __launch_bounds__(256) void k_fft_axis(const InT* in, cplx<T>* out, i
     const long base = long(blockIdx.z) * sComp + long(other) * sOther + k2_0;
 
     for (int i = tid; i < LEN; i += Cfg::THREADS) tw[i] = twg[i];
-    double cO = 1.0;
-    if constexpr (FIRST) cO = cOther[other];
-    for (int idx = tid; idx < LEN * W; idx += Cfg::THREADS) {
-        const int a = idx / W, w = idx % W;
-        cplx<T> v = {T(0), T(0)};
-        if (k2_0 + w < H) {
-            const long e = base + long(a) * sAxis + w;
-            if constexpr (FIRST) {
-                const double re = double(in[2 * e]);
-                const double im = double(in[2 * e + 1]);
-                const double m = (cAxis[a] * cO) * c2[k2_0 + w];
-                v = {T(re * m), T(im * m)};
-            } else {
-                v = reinterpret_cast<const cplx<T>*>(in)[e];
-            }
+    // Thread tid always handles line w = tid % W; it moves PER elements of that
+    // line (rows a = q * RSTEP + tid / W), all loads issued before any store.
+    constexpr int RSTEP = Cfg::TEAM;
+    constexpr int PER = LEN / RSTEP;
+    static_assert(LEN % RSTEP == 0, "line length must be a multiple of the row step");
+    const int w = tid % W;
+    const int a0 = tid / W;
+    const bool valid = k2_0 + w < H;
+    const long lane_base = base + (valid ? w : 0) + long(a0) * sAxis;
+    const long step = long(RSTEP) * sAxis;
+    cplx<T> v[PER];
+    if constexpr (FIRST) {
+        const double cw = (valid ? c2[k2_0 + w] : 0.0);
+        const double cO = cOther[other];
+        double re[PER], im[PER], ca[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const long e = lane_base + q * step;
+            re[q] = double(in[2 * e]);
+            im[q] = double(in[2 * e + 1]);
+            ca[q] = cAxis[q * RSTEP + a0];
         }
-        lines[w * LP + a] = v;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const double m = (ca[q] * cO) * cw;
+            v[q] = {T(re[q] * m), T(im[q] * m)};
+        }
+    } else {
+        const cplx<T>* src = reinterpret_cast<const cplx<T>*>(in);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) v[q] = src[lane_base + q * step];
     }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) lines[w * LP + q * RSTEP + a0] = v[q];
     __syncthreads();
     fft_stages<T, LEN, Cfg::TEAM, 1, 1>(lines + (tid / Cfg::TEAM) * LP, tw, tid % Cfg::TEAM);
-    for (int idx = tid; idx < LEN * W; idx += Cfg::THREADS) {
-        const int a = idx / W, w = idx % W;
-        if (k2_0 + w < H) out[base + long(a) * sAxis + w] = lines[w * LP + a];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = lines[w * LP + q * RSTEP + a0];
+    if (valid) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) out[lane_base + q * step] = v[q];
     }
 }
 
@@ -237,13 +258,27 @@ __global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, O
     const long compStride = nlines * H;
 
     for (int i = tid; i < 2 * M; i += Cfg::THREADS) tw[i] = twg[i];
-    // load every (line, component) row of H complex values
-    for (int idx = tid; idx < NL * H; idx += Cfg::THREADS) {
-        const int f = idx / H, k = idx % H;
-        const int l = f / C, c = f % C;
-        cplx<T> v = {T(0), T(0)};
-        if (line0 + l < nlines) v = work[long(c) * compStride + (line0 + l) * H + k];
-        zb[f * LP + k] = v;
+    // load every (line, component) row of H complex values; all loads of a
+    // thread are issued before its LDS stores
+    constexpr int ITER = (NL * H + Cfg::THREADS - 1) / Cfg::THREADS;
+    {
+        cplx<T> v[ITER];
+#pragma unroll
+        for (int q = 0; q < ITER; ++q) {
+            const int idx = q * Cfg::THREADS + tid;
+            const int f = idx / H, k = idx - (idx / H) * H;
+            const int l = f / C, c = f - (f / C) * C;
+            const bool ok = idx < NL * H && line0 + l < nlines;
+            v[q] = work[ok ? long(c) * compStride + (line0 + l) * H + k : 0];
+        }
+#pragma unroll
+        for (int q = 0; q < ITER; ++q) {
+            const int idx = q * Cfg::THREADS + tid;
+            if (idx < NL * H) {
+                const int f = idx / H, k = idx - (idx / H) * H;
+                zb[f * LP + k] = v[q];
+            }
+        }
     }
     __syncthreads();
     // even/odd twist: Z[k] = (X[k] + conj X[M-k]) + i e^{2 pi i k/(2M)} (X[k] - conj X[M-k]),
@@ -348,7 +383,7 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
     case L: {                                                                                      \
         *Wout = StridedCfg<T, L>::W;                                                               \
         grid.x = (H + StridedCfg<T, L>::W - 1) / StridedCfg<T, L>::W;                              \
-        hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), grid, dim3(256), 0, s, in, out, H, sAxis, \
+        hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), grid, dim3(StridedCfg<T, L>::THREADS), 0, s, in, out, H, sAxis, \
                            sOther, sComp, cAxis, cOther, c2, tw);                                  \
         break;                                                                                     \
     }
@@ -435,14 +470,21 @@ bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_
     const long sComp = long(n0) * n1 * H;
     int W = 0;
     // pass A: axis 0 (stride n1*H), other = k1 (stride H)
+    {
+    StageTimer tm(ctx, "fft_axis0", s);
     BSI_TRY((launch_axis<T, InT, true>(n0, dim3(1, n1, C), uhat, work, H, long(n1) * H, long(H), sComp,
                                        c0, c1, c2, static_cast<const cplx<T>*>(tw0), s, &W)));
+    }
     // pass B: axis 1 (stride H), other = k0 (stride n1*H), in place
+    {
+    StageTimer tm(ctx, "fft_axis1", s);
     BSI_TRY((launch_axis<T, T, false>(n1, dim3(1, n0, C), reinterpret_cast<const T*>(work), work, H,
                                       long(H), long(n1) * H, sComp, nullptr, nullptr, nullptr,
                                       static_cast<const cplx<T>*>(tw1), s, &W)));
+    }
     // pass C: c2r along axis 2
     const int M = n2 / 2;
+    StageTimer tm(ctx, "fft_c2r", s);
     if (C == 1)
         return launch_c2r<T, OutT, 1>(M, work, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->padlo,
                                       static_cast<const cplx<T>*>(tw2), s);

@@ -58,10 +58,11 @@ def test_gather_matches_oracle(ctx, n, C, N, coef):
         f.set_coefficients(dev(grid))
         back = host(f.get_coefficients())
         assert np.array_equal(back, stored)
-        for cfg in (None, (0, 256, 0), (4, 128, 1), (8, 64, 1), (2, 192, 0)):
+        for cfg in (None, (0, 256, 0, 0), (4, 128, 1, 0), (8, 64, 1, 0), (2, 192, 0, 0),
+                    (6, 256, 1, 0), (12, 128, 1, 0), (8, 256, 1, 1), (16, 256, 1, 0)):
             c = None
             if cfg is not None:
-                c = bsi.EvalConfig(sort_tile=cfg[0], block=cfg[1], xcd_remap=cfg[2])
+                c = bsi.EvalConfig(sort_tile=cfg[0], block=cfg[1], xcd_remap=cfg[2], variant=cfg[3])
             u, g = f.eval(dev(pos), cfg=c)
             u, g = host(u), host(g)
             eu, eg = rel_err(u, want_u), rel_err(g, want_g)
@@ -79,9 +80,10 @@ def test_gather_results_independent_of_tuning(ctx):
     with bsi.Field(ctx, 32, 3, 6, bsi.BSI_F32) as f:
         f.set_coefficients(dev(grid))
         ref = None
-        for tile in (0, 1, 2, 4, 8, 16, 32):
-            for block in (64, 256):
-                u, g = f.eval(dev(pos), cfg=bsi.EvalConfig(sort_tile=tile, block=block, xcd_remap=1))
+        for tile in (0, 1, 2, 4, 6, 8, 10, 12, 16, 32):
+            for block, variant in ((64, 0), (256, 0), (128, 1)):
+                u, g = f.eval(dev(pos), cfg=bsi.EvalConfig(sort_tile=tile, block=block, xcd_remap=1,
+                                                           variant=variant))
                 cur = (host(u), host(g))
                 if ref is None:
                     ref = cur
