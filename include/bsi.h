@@ -84,9 +84,12 @@ typedef struct bsi_eval_config {
     int32_t sort_tile;   /* cells per Morton tile edge for particle binning; 0 = no binning */
     int32_t block;       /* threads per workgroup of the gather kernel (64..1024, multiple of 64) */
     int32_t xcd_remap;   /* 1 = map consecutive binned particle blocks onto one XCD            */
-    int32_t variant;     /* 0 = LDS-tiled gather when sort_tile > 0 (one workgroup per Morton
-                            tile, tile sizes 4, 6, 8, 10, 12, 16 within 64 KB of LDS);
-                            1 = one thread per particle reading the grid directly */
+    int32_t variant;     /* 0 = LDS-tiled gather when sort_tile > 0 and the tile fits (sizes 4, 6,
+                            8, 12, 16 whose block is at most 64 KB of LDS and whose origin is
+                            16-byte aligned); otherwise, and for 1, one thread per particle
+                            reading the grid directly */
+    int32_t tiles_per_group; /* consecutive Morton tiles walked by one tiled workgroup (0 = 4) */
+    int32_t reserved[3];     /* must be 0 */
 } bsi_eval_config;
 
 typedef struct bsi_ctx bsi_ctx;

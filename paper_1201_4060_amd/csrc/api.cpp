@@ -206,6 +206,8 @@ bsi_status bsi_ctx_create(int device, void* hip_stream, bsi_ctx** out) {
     ctx->tuned.sort_tile = 8;
     ctx->tuned.block = 256;
     ctx->tuned.xcd_remap = 1;
+    ctx->tuned.variant = 0;
+    ctx->tuned.tiles_per_group = 2;
     *out = ctx;
     return BSI_OK;
 }
@@ -289,7 +291,13 @@ bsi_status bsi_field_create(bsi_ctx* ctx, const bsi_field_desc* desc, bsi_field*
         f->L[d] = desc->length[d] == 0.0 ? 2.0 * 3.141592653589793 : desc->length[d];
         f->inv_h[d] = double(f->n[d]) / f->L[d];
     }
-    f->grid_bytes = size_t(f->P[0]) * f->P[1] * f->P[2] * f->C * dtype_size(desc->coef);
+    {
+        const int vec = int(16 / dtype_size(desc->coef));
+        f->pitch2 = (f->P[2] * f->C + vec - 1) / vec * vec;
+    }
+    // rows padded to 16 B so tile rows load as 16-byte vectors; 4 KiB of slack
+    // after the last row absorbs vector over-reads of partial tiles
+    f->grid_bytes = size_t(f->P[0]) * f->P[1] * f->pitch2 * dtype_size(desc->coef) + 4096;
     if (hipMalloc(&f->grid, f->grid_bytes) != hipSuccess) {
         (void)hipGetLastError();
         delete f;
@@ -303,7 +311,7 @@ bsi_status bsi_field_create(bsi_ctx* ctx, const bsi_field_desc* desc, bsi_field*
         set_error("counter allocation failed");
         return BSI_E_NOMEM;
     }
-    if (hipMemset(f->counters, 0, 64) != hipSuccess) {
+    if (hipMemset(f->counters, 0, 64) != hipSuccess || hipMemset(f->grid, 0, f->grid_bytes) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(f->grid);
         (void)hipFree(f->counters);

@@ -163,6 +163,7 @@ struct bsi_field {
     int n[3] = {0, 0, 0};
     int P[3] = {0, 0, 0};  // padded extents n + N - 1
     int padlo = 1;         // ghost planes below index 0 (N/2 - 1)
+    int pitch2 = 0;        // elements between consecutive (p0, p1) rows: P2*C rounded up to 16 B
     double L[3] = {0, 0, 0};
     double inv_h[3] = {0, 0, 0};
     void* grid = nullptr;

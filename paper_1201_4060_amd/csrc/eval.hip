@@ -1,6 +1,7 @@
 // Evaluation on the GPU: position -> cell/offset, Morton binning, and the
 // per-particle gather + tensor contraction (Sections 2, 3, 5; Table 1).
 #include <algorithm>
+#include <utility>
 
 #include "common.hpp"
 
@@ -164,11 +165,22 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const uint32_t* __res
     }
 }
 
+// perm[dst] = p and, when pos_sorted is given, a copy of the particle's
+// position at its binned slot (so that the gather reads binned positions
+// contiguously instead of through perm).
 __global__ void k_bin_scatter(long P, const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
-                              const uint32_t* __restrict__ offs, uint32_t* __restrict__ perm) {
+                              const uint32_t* __restrict__ offs, uint32_t* __restrict__ perm,
+                              const double* __restrict__ pos, double* __restrict__ pos_sorted) {
     const long p = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (p >= P) return;
-    perm[offs[key[p]] + rank[p]] = uint32_t(p);
+    const uint32_t dst = offs[key[p]] + rank[p];
+    perm[dst] = uint32_t(p);
+    if (pos_sorted) {
+        const double x0 = pos[3 * p], x1 = pos[3 * p + 1], x2 = pos[3 * p + 2];
+        pos_sorted[3 * long(dst)] = x0;
+        pos_sorted[3 * long(dst) + 1] = x1;
+        pos_sorted[3 * long(dst) + 2] = x2;
+    }
 }
 
 __global__ void k_fill_u32(uint32_t* p, long n, uint32_t v) {
@@ -215,6 +227,7 @@ struct GatherArgs {
     const void* grid;
     const double* pos;
     const uint32_t* perm;    // binned order, or nullptr
+    const double* pos_sorted;  // positions in binned order (tiled kernel), or nullptr
     const uint32_t* hist;    // particles per bucket (tiled kernel)
     const uint32_t* offs;    // first binned index per bucket (tiled kernel)
     void* u;
@@ -223,9 +236,11 @@ struct GatherArgs {
     long P;
     int n0, n1, n2;
     int P1, P2;  // padded extents of axes 1 and 2
+    int pitch2;  // elements between consecutive (p0, p1) rows of the grid
     double ih0, ih1, ih2;
     int xcd_remap;
     uint32_t nbuckets_finite;
+    uint32_t tiles_per_group;
 };
 
 __device__ __forceinline__ long logical_block(int remap) {
@@ -254,14 +269,14 @@ __device__ __forceinline__ void write_nan(const GatherArgs& a, long p) {
 
 // Cell and weights of particle p (Section 5 stencil, Section 2 weights).
 template <int N, typename AT>
-__device__ __forceinline__ bool particle_setup(const GatherArgs& a, long p, int* cell, AT (*w)[N],
-                                               AT (*wd)[N]) {
+__device__ __forceinline__ bool particle_setup_x(const GatherArgs& a, const double* x, int* cell,
+                                                 AT (*w)[N], AT (*wd)[N]) {
     const int n[3] = {a.n0, a.n1, a.n2};
     const double ih[3] = {a.ih0, a.ih1, a.ih2};
     double t[3];
     bool ok = true;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) ok = cell_of(a.pos[3 * p + d], ih[d], n[d], cell[d], t[d]) && ok;
+    for (int d = 0; d < 3; ++d) ok = cell_of(x[d], ih[d], n[d], cell[d], t[d]) && ok;
     if (!ok) return false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -271,6 +286,13 @@ __device__ __forceinline__ bool particle_setup(const GatherArgs& a, long p, int*
         for (int k = 0; k < N; ++k) wd[d][k] *= s;
     }
     return true;
+}
+
+template <int N, typename AT>
+__device__ __forceinline__ bool particle_setup(const GatherArgs& a, long p, int* cell, AT (*w)[N],
+                                               AT (*wd)[N]) {
+    const double x[3] = {a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]};
+    return particle_setup_x<N, AT>(a, x, cell, w, wd);
 }
 
 // Tensor contraction of the N^3 (x C) local coefficients with the weights.
@@ -286,55 +308,79 @@ struct Partial {
     AT u[C], g0[C], g1[C], g2[C];
 };
 
-template <int N, typename CT, typename AT, int C, bool GRAD, int IA0, int IA1, bool FENCE = false,
-          typename RowFn>
-__device__ __forceinline__ void contract_part(const AT (*w)[N], const AT (*wd)[N], RowFn row,
-                                              Partial<AT, C>& out) {
+// One axis-0 plane: rows row(ib), ib < N, reduced along axis 2 then axis 1,
+// accumulated into out with the plane's axis-0 weights w0k, wd0k.
+template <int N, typename CT, typename AT, int C, bool GRAD, bool FENCE, typename PlaneRowFn>
+__device__ __forceinline__ void contract_plane(AT w0k, AT wd0k, const AT (*w)[N], const AT (*wd)[N],
+                                               PlaneRowFn row, Partial<AT, C>& out) {
+    AT v[C], v1[C], v2[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) out.u[c] = out.g0[c] = out.g1[c] = out.g2[c] = AT(0);
+    for (int c = 0; c < C; ++c) v[c] = v1[c] = v2[c] = AT(0);
 #pragma unroll
-    for (int ia = IA0; ia < IA1; ++ia) {
-        AT v[C], v1[C], v2[C];
+    for (int ib = 0; ib < N; ++ib) {
+        const auto* r = row(ib);
+        CT raw[N * C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) v[c] = v1[c] = v2[c] = AT(0);
+        for (int e = 0; e < N * C; ++e) raw[e] = r[e];
+        AT tr[C], trd[C];
 #pragma unroll
-        for (int ib = 0; ib < N; ++ib) {
-            const auto* r = row(ia, ib);
-            CT raw[N * C];
+        for (int c = 0; c < C; ++c) tr[c] = trd[c] = AT(0);
 #pragma unroll
-            for (int e = 0; e < N * C; ++e) raw[e] = r[e];
-            AT tr[C], trd[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) tr[c] = trd[c] = AT(0);
-#pragma unroll
-            for (int e = 0; e < N; ++e) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const AT val = widen<CT, AT>(raw[e * C + c]);
-                    tr[c] += w[2][e] * val;
-                    if constexpr (GRAD) trd[c] += wd[2][e] * val;
-                }
-            }
+        for (int e = 0; e < N; ++e) {
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                v[c] += w[1][ib] * tr[c];
-                if constexpr (GRAD) {
-                    v1[c] += wd[1][ib] * tr[c];
-                    v2[c] += w[1][ib] * trd[c];
-                }
+                const AT val = widen<CT, AT>(raw[e * C + c]);
+                tr[c] += w[2][e] * val;
+                if constexpr (GRAD) trd[c] += wd[2][e] * val;
             }
-            // LDS rows: keep one row's values live at a time (bounded registers)
-            if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            out.u[c] += w[0][ia] * v[c];
+            v[c] += w[1][ib] * tr[c];
             if constexpr (GRAD) {
-                out.g0[c] += wd[0][ia] * v[c];
-                out.g1[c] += w[0][ia] * v1[c];
-                out.g2[c] += w[0][ia] * v2[c];
+                v1[c] += wd[1][ib] * tr[c];
+                v2[c] += w[1][ib] * trd[c];
             }
         }
+        if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        out.u[c] += w0k * v[c];
+        if constexpr (GRAD) {
+            out.g0[c] += wd0k * v[c];
+            out.g1[c] += w0k * v1[c];
+            out.g2[c] += w0k * v2[c];
+        }
+    }
+}
+
+// NIA consecutive axis-0 planes: w0[k], wd0[k] are the axis-0 weights of
+// plane k and row(k, ib) its rows; accumulation order is k = 0..NIA-1.
+// FENCE (LDS-resident rows): planes run as a loop so that only one plane's
+// rows are live at a time; otherwise everything is unrolled.
+template <int N, typename CT, typename AT, int C, bool GRAD, int NIA, bool FENCE = false, typename RowFn>
+__device__ __forceinline__ void contract_planes(const AT* w0, const AT* wd0, const AT (*w)[N],
+                                                const AT (*wd)[N], RowFn row, Partial<AT, C>& out) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) out.u[c] = out.g0[c] = out.g1[c] = out.g2[c] = AT(0);
+    if constexpr (FENCE) {
+#pragma unroll 1
+        for (int k = 0; k < NIA; ++k) {
+            AT w0k = w0[0], wd0k = wd0[0];
+#pragma unroll
+            for (int q = 1; q < NIA; ++q) {
+                w0k = (k == q) ? w0[q] : w0k;
+                wd0k = (k == q) ? wd0[q] : wd0k;
+            }
+            contract_plane<N, CT, AT, C, GRAD, true>(w0k, wd0k, w, wd, [&](int ib) { return row(k, ib); },
+                                                    out);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NIA; ++k)
+            contract_plane<N, CT, AT, C, GRAD, false>(w0[k], wd0[k], w, wd,
+                                                     [&](int ib) { return row(k, ib); }, out);
     }
 }
 
@@ -359,8 +405,9 @@ template <int N, typename CT, typename AT, int C, bool GRAD, bool FENCE = false,
 __device__ __forceinline__ void contract_and_store(const GatherArgs& a, long p, const AT (*w)[N],
                                                    const AT (*wd)[N], RowFn row) {
     Partial<AT, C> lo, hi;
-    contract_part<N, CT, AT, C, GRAD, 0, N / 2, FENCE>(w, wd, row, lo);
-    contract_part<N, CT, AT, C, GRAD, N / 2, N, FENCE>(w, wd, row, hi);
+    contract_planes<N, CT, AT, C, GRAD, N / 2, FENCE>(w[0], wd[0], w, wd, row, lo);
+    contract_planes<N, CT, AT, C, GRAD, N / 2, FENCE>(
+        w[0] + N / 2, wd[0] + N / 2, w, wd, [&](int k, int ib) { return row(N / 2 + k, ib); }, hi);
     store_sum<AT, C, GRAD>(a, p, lo, hi);
 }
 
@@ -379,10 +426,10 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
         atomicAdd(a.nonfinite, 1ull);
         return;
     }
-    const CT* base = static_cast<const CT*>(a.grid) +
-                     ((long(cell[0]) * a.P1 + cell[1]) * a.P2 + cell[2]) * C;
-    const long rowA = long(a.P1) * a.P2 * C;
-    const long rowB = long(a.P2) * C;
+    const CT* base = static_cast<const CT*>(a.grid) + (long(cell[0]) * a.P1 + cell[1]) * a.pitch2 +
+                     long(cell[2]) * C;
+    const long rowA = long(a.P1) * a.pitch2;
+    const long rowB = a.pitch2;
     contract_and_store<N, CT, AT, C, GRAD>(a, p, w, wd,
                                            [&](int ia, int ib) { return base + ia * rowA + ib * rowB; });
 }
@@ -396,12 +443,21 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v) {  // inverse of spread
     return v;
 }
 
+// Geometry of one LDS tile: the (T+N-1)^3 block of the ghost-padded grid that
+// holds the stencils of a T^3 tile of cells, each row of (T+N-1)*C elements
+// rounded up to whole 16-byte chunks.
 template <int N, typename CT, int C, int T>
 struct TileGeom {
-    static constexpr int R = T + N - 1;               // LDS block edge (points)
-    static constexpr int ROW = R * C;                 // elements per LDS row
-    static constexpr int ELEMS = R * R * ROW;
-    static constexpr int BYTES = ELEMS * int(sizeof(CT));
+    static constexpr int R = T + N - 1;
+    static constexpr int VEC = 16 / int(sizeof(CT));   // elements per 16-byte chunk
+    static constexpr int CH = (R * C + VEC - 1) / VEC;  // chunks per row
+    static constexpr int LROW = CH * VEC;               // LDS row pitch (elements)
+    static constexpr int ROWS = R * R;
+    static constexpr int SLOTS = ROWS * CH;
+    static constexpr int PER = (SLOTS + 63) / 64;       // chunks per lane
+    static constexpr int BYTES = SLOTS * 16;
+    // tile origins must start on 16-byte boundaries inside a row
+    static constexpr bool ALIGNED = (T * C * int(sizeof(CT))) % 16 == 0;
 };
 
 template <typename AT>
@@ -409,107 +465,177 @@ __device__ __forceinline__ AT shfl_xor1(AT v) {
     return __shfl_xor(v, 1, 64);
 }
 
-// LDS-tiled variant: one 64-lane workgroup per Morton tile of T^3 cells.  The
-// tile's (T+N-1)^3 block of the ghost-padded grid is staged in LDS with
-// coalesced loads (compile-time geometry, loads issued back to back), then the
-// tile's binned particles are evaluated from LDS: one lane per particle, or
-// two lanes per particle (one half of the axis-0 sum each, combined with a
-// lane shuffle) when the tile holds at most 32 particles.
-template <int N, typename CT, int C, bool GRAD, int T>
-__global__ __launch_bounds__(64) void k_gather_tiled(GatherArgs a) {
+// Barrier for LDS only: orders the wavefront's LDS accesses without waiting for
+// outstanding global loads (the next tile's prefetch stays in flight).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ uint32_t next_tile(const GatherArgs& a, uint32_t b, uint32_t end) {
+    while (b < end && a.hist[b] == 0) ++b;
+    return b;
+}
+
+// Issue the 16-byte loads of the LDS block of tile `bucket` into registers.
+// Rows outside the padded grid (partial tiles only; never read by a particle)
+// load the tile origin instead; chunks past a row's end read the next row or
+// the allocation's slack.  The slots are expanded at compile time (no loop)
+// so that the register array is indexed by constants only.
+template <int N, typename CT, int C, int T>
+struct TileLoad {
+    using G = TileGeom<N, CT, C, T>;
+    const uint4* g;
+    int p0v, p1v, lim0, lim1, lane;
+
+    __device__ __forceinline__ TileLoad(const GatherArgs& a, uint32_t bucket, int lane_) : lane(lane_) {
+        const int o0 = int(compact3(bucket >> 2)) * T;
+        const int o1 = int(compact3(bucket >> 1)) * T;
+        const int o2 = int(compact3(bucket)) * T;
+        lim0 = a.n0 + N - 1 - o0;
+        lim1 = a.n1 + N - 1 - o1;
+        g = reinterpret_cast<const uint4*>(static_cast<const CT*>(a.grid) +
+                                           (long(o0) * a.P1 + o1) * long(a.pitch2) + long(o2) * C);
+        p1v = a.pitch2 / G::VEC;  // row pitch in chunks (offsets inside a tile stay < 2^31)
+        p0v = a.P1 * p1v;
+    }
+    template <int Q>
+    __device__ __forceinline__ uint4 slot() const {
+        const int sl = Q * 64 + lane;
+        const int row = sl / G::CH;
+        const int ch = sl - row * G::CH;
+        const int r0 = row / G::R;
+        const int r1 = row - r0 * G::R;
+        const bool ok = sl < G::SLOTS && r0 < lim0 && r1 < lim1;
+        return g[ok ? r0 * p0v + r1 * p1v + ch : 0];
+    }
+    template <size_t... Q>
+    __device__ __forceinline__ void issue(uint4 (&pre)[G::PER], std::index_sequence<Q...>) const {
+        ((pre[Q] = slot<int(Q)>()), ...);
+    }
+};
+
+template <int N, typename CT, int C, int T>
+__device__ __forceinline__ void tile_issue(const GatherArgs& a, uint32_t bucket,
+                                           uint4 (&pre)[TileGeom<N, CT, C, T>::PER], int lane) {
+    TileLoad<N, CT, C, T> tl(a, bucket, lane);
+    tl.issue(pre, std::make_index_sequence<TileGeom<N, CT, C, T>::PER>{});
+}
+
+template <int N, typename CT, int C, int T, size_t... Q>
+__device__ __forceinline__ void tile_store_impl(uint4* lds, const uint4 (&pre)[TileGeom<N, CT, C, T>::PER],
+                                                int lane, std::index_sequence<Q...>) {
+    using G = TileGeom<N, CT, C, T>;
+    (((int(Q) * 64 + 64 <= G::SLOTS || int(Q) * 64 + lane < G::SLOTS) ? (void)(lds[Q * 64 + lane] = pre[Q])
+                                                                      : (void)0),
+     ...);
+}
+
+template <int N, typename CT, int C, int T>
+__device__ __forceinline__ void tile_store(uint4* lds, const uint4 (&pre)[TileGeom<N, CT, C, T>::PER],
+                                           int lane) {
+    tile_store_impl<N, CT, C, T>(lds, pre, lane, std::make_index_sequence<TileGeom<N, CT, C, T>::PER>{});
+}
+
+// LDS-tiled variant.  One workgroup of B threads walks `tiles_per_group`
+// consecutive Morton tiles (T^3 cells each).  For each tile, all 16-byte loads
+// of its LDS block are issued at once (one memory round trip) together with
+// the tile's binned positions (contiguous); the block is stored to LDS and the
+// particles are evaluated from it: two lanes per particle (one half of the
+// axis-0 sum each, combined with a lane shuffle) while the tile holds at most
+// B/2 particles, one lane per particle otherwise.
+template <int N, typename CT, int C, bool GRAD, int T, int B>
+__global__ __launch_bounds__(B) void k_gather_tiled(GatherArgs a) {
     using AT = typename Acc<CT>::type;
     using G = TileGeom<N, CT, C, T>;
-    // Loads: lane = (sub-row, element); one pass covers RPP rows of ROW
-    // elements; all rows of one r0-plane are issued before their LDS stores.
-    static_assert(G::ROW <= 64, "tile row wider than a wavefront");
-    constexpr int RPP = 64 / G::ROW;
-    constexpr int NR = (G::R + RPP - 1) / RPP;
-    __shared__ CT tile[G::ELEMS];
-    const int lane = threadIdx.x;
-    const uint32_t bucket = uint32_t(logical_block(a.xcd_remap));
-    const uint32_t count = a.hist[bucket];
-    if (count == 0) return;
-    const uint32_t start = a.offs[bucket];
-    if (bucket == a.nbuckets_finite) {  // particles without a cell
-        for (uint32_t j = lane; j < count; j += 64) write_nan<AT, C, GRAD>(a, long(a.perm[start + j]));
-        if (lane == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
-        return;
-    }
-    const int o0 = int(compact3(bucket >> 2)) * T;
-    const int o1 = int(compact3(bucket >> 1)) * T;
-    const int o2 = int(compact3(bucket)) * T;
-    // valid extent of the block (the last tile along an axis may be partial)
-    const int lim0 = a.n0 + N - 1 - o0;        // rows r0 < lim0 exist in the padded grid
-    const int lim1 = a.n1 + N - 1 - o1;
-    const int limE = (a.n2 + N - 1 - o2) * C;  // elements e < limE exist in a row
-    const CT* g = static_cast<const CT*>(a.grid) + (long(o0) * a.P1 + o1) * long(a.P2) * C + long(o2) * C;
-    // offsets inside one tile block stay below 2^31 (R * P1 * P2 * C elements)
-    const int pitch1 = a.P2 * C;
-    const int pitch0 = a.P1 * pitch1;
-    // Every lane loads unconditionally; positions outside the padded grid (only
-    // in partial tiles, and never read by a particle) load the tile origin.
-    const int sub = lane / G::ROW;
-    const int e = lane - sub * G::ROW;
-    if (sub < RPP) {
-        const bool e_ok = e < limE;
-        const int lane_off = sub * pitch1 + e;
-        const int step = RPP * pitch1;
-        const int r0n = min(G::R, lim0);
-        for (int r0 = 0; r0 < r0n; ++r0) {
-            const int base0 = r0 * pitch0 + lane_off;
-            CT v[NR];
+    constexpr int PERB = (G::SLOTS + B - 1) / B;
+    __shared__ uint4 tile_v[PERB * B];
+    const CT* tile = reinterpret_cast<const CT*>(tile_v);
+    const int tid = threadIdx.x;
+    const uint32_t nbt = a.nbuckets_finite + 1;
+    const uint32_t b0 = uint32_t(logical_block(a.xcd_remap)) * a.tiles_per_group;
+    const uint32_t b1 = min(b0 + a.tiles_per_group, nbt);
+    for (uint32_t cur = next_tile(a, b0, b1); cur < b1; cur = next_tile(a, cur + 1, b1)) {
+        const uint32_t count = a.hist[cur];
+        const uint32_t start = a.offs[cur];
+        if (cur == a.nbuckets_finite) {  // particles without a cell (the last bucket)
+            for (uint32_t j = tid; j < count; j += B) write_nan<AT, C, GRAD>(a, long(a.perm[start + j]));
+            if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
+            break;
+        }
+        const int o0 = int(compact3(cur >> 2)) * T;
+        const int o1 = int(compact3(cur >> 1)) * T;
+        const int o2 = int(compact3(cur)) * T;
+        const bool pair = count <= uint32_t(B / 2);
+        const int stride = pair ? B / 2 : B;
+        const uint32_t jlane = pair ? uint32_t(tid >> 1) : uint32_t(tid);
+        const int half = pair ? (tid & 1) : 0;
+        {
+            // slots tid, tid + B, ... of the block (compile-time expanded)
+            TileLoad<N, CT, C, T> tl(a, cur, 0);
+            uint4 pre[PERB];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const int r1 = k * RPP + sub;
-                const bool ok = e_ok && r1 < lim1 && r1 < G::R;
-                v[k] = g[ok ? base0 + k * step : 0];
+            for (int q = 0; q < PERB; ++q) {
+                const int sl = q * B + tid;
+                const int row = sl / G::CH;
+                const int ch = sl - row * G::CH;
+                const int r0 = row / G::R;
+                const int r1 = row - r0 * G::R;
+                const bool ok = sl < G::SLOTS && r0 < tl.lim0 && r1 < tl.lim1;
+                pre[q] = tl.g[ok ? r0 * tl.p0v + r1 * tl.p1v + ch : 0];
             }
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const int r1 = k * RPP + sub;
-                if (r1 < G::R) tile[(r0 * G::R + r1) * G::ROW + e] = v[k];
-            }
+            for (int q = 0; q < PERB; ++q) tile_v[q * B + tid] = pre[q];
         }
-    }
-    __syncthreads();
-    auto particle_rows = [&](const int* cell) {
-        const CT* base = tile + ((cell[0] - o0) * G::R + (cell[1] - o1)) * G::ROW + (cell[2] - o2) * C;
-        return [base](int ia, int ib) { return base + (ia * G::R + ib) * G::ROW; };
-    };
-    if (count <= 32) {
-        const uint32_t j = uint32_t(lane >> 1);
-        const int half = lane & 1;
-        const bool active = j < count;
-        const long p = active ? long(a.perm[start + j]) : 0;
-        int cell[3] = {o0, o1, o2};
-        AT w[3][N], wd[3][N];
-        if (active) particle_setup<N, AT>(a, p, cell, w, wd);
-        else {
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int k = 0; k < N; ++k) w[d][k] = wd[d][k] = AT(0);
-        }
-        const auto rows = particle_rows(cell);
-        Partial<AT, C> mine, other;
-        if (half == 0) contract_part<N, CT, AT, C, GRAD, 0, N / 2, true>(w, wd, rows, mine);
-        else contract_part<N, CT, AT, C, GRAD, N / 2, N, true>(w, wd, rows, mine);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            other.u[c] = shfl_xor1(mine.u[c]);
-            other.g0[c] = shfl_xor1(mine.g0[c]);
-            other.g1[c] = shfl_xor1(mine.g1[c]);
-            other.g2[c] = shfl_xor1(mine.g2[c]);
-        }
-        if (active && half == 0) store_sum<AT, C, GRAD>(a, p, mine, other);
-    } else {
-        for (uint32_t j = lane; j < count; j += 64) {
-            const long p = long(a.perm[start + j]);
+        lds_barrier();
+        for (uint32_t j0 = 0; j0 < count; j0 += uint32_t(stride)) {
+            // a wavefront without any particle in this round skips it (uniform);
+            // inside a working wavefront, lanes past the end evaluate the tile's
+            // first particle and store nothing
+            if (j0 + uint32_t((pair ? 32 : 64) * (tid / 64)) >= count) continue;
+            const uint32_t j = j0 + jlane;
+            const bool active = j < count;
+            const uint32_t jj = start + (active ? j : 0u);
+            const long p = long(a.perm[jj]);
+            const double x[3] = {a.pos_sorted[3 * long(jj)], a.pos_sorted[3 * long(jj) + 1],
+                                 a.pos_sorted[3 * long(jj) + 2]};
             int cell[3];
             AT w[3][N], wd[3][N];
-            particle_setup<N, AT>(a, p, cell, w, wd);  // finite by construction of the bucket
-            contract_and_store<N, CT, AT, C, GRAD, true>(a, p, w, wd, particle_rows(cell));
+            particle_setup_x<N, AT>(a, x, cell, w, wd);  // finite by construction of the bucket
+            const CT* base = tile + ((cell[0] - o0) * G::R + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * C;
+            auto rows = [base](int ia, int ib) { return base + (ia * G::R + ib) * G::LROW; };
+            if (pair) {
+                // both lanes of a pair run the same instructions: lane `half`
+                // takes planes half*N/2 .. half*N/2 + N/2 - 1
+                const int ia0 = half * (N / 2);
+                AT w0s[N / 2], wd0s[N / 2];
+#pragma unroll
+                for (int k = 0; k < N / 2; ++k) {
+                    w0s[k] = half ? w[0][N / 2 + k] : w[0][k];
+                    wd0s[k] = half ? wd[0][N / 2 + k] : wd[0][k];
+                }
+                Partial<AT, C> mine, other;
+                contract_planes<N, CT, AT, C, GRAD, N / 2, true>(
+                    w0s, wd0s, w, wd, [&](int k, int ib) { return rows(ia0 + k, ib); }, mine);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    other.u[c] = shfl_xor1(mine.u[c]);
+                    other.g0[c] = shfl_xor1(mine.g0[c]);
+                    other.g1[c] = shfl_xor1(mine.g1[c]);
+                    other.g2[c] = shfl_xor1(mine.g2[c]);
+                }
+                if (active && half == 0) store_sum<AT, C, GRAD>(a, p, mine, other);
+            } else {
+                Partial<AT, C> lo, hi;
+                contract_planes<N, CT, AT, C, GRAD, N / 2, true>(w[0], wd[0], w, wd, rows, lo);
+                contract_planes<N, CT, AT, C, GRAD, N / 2, true>(
+                    w[0] + N / 2, wd[0] + N / 2, w, wd, [&](int k, int ib) { return rows(N / 2 + k, ib); },
+                    hi);
+                if (active) store_sum<AT, C, GRAD>(a, p, lo, hi);
+            }
         }
+        lds_barrier();
     }
 }
 
@@ -550,43 +676,68 @@ void launch_gather_ct(int N, int C, const GatherArgs& ga, bool grad, unsigned nb
     }
 }
 
-constexpr int TILE_LDS_LIMIT = 64 * 1024;
+constexpr int TILE_LDS_LIMIT = 64 * 1024;  // static LDS per workgroup
 
 template <int N, typename CT, int C, int T>
-bool launch_tiled_T(const GatherArgs& ga, bool grad, unsigned nb, unsigned block, hipStream_t s) {
-    if constexpr (TileGeom<N, CT, C, T>::BYTES > TILE_LDS_LIMIT) {
+constexpr bool tile_ok() {
+    return TileGeom<N, CT, C, T>::BYTES <= TILE_LDS_LIMIT && TileGeom<N, CT, C, T>::ALIGNED;
+}
+
+// 64 threads for small tiles, 256 for tiles whose block fills the LDS budget
+template <int N, typename CT, int C, int T>
+constexpr int tile_block() {
+    return TileGeom<N, CT, C, T>::SLOTS >= 1536 ? 256 : 64;
+}
+
+template <int N, typename CT, int C, int T>
+bool launch_tiled_T(const GatherArgs& ga, bool grad, unsigned nb, hipStream_t s) {
+    if constexpr (!tile_ok<N, CT, C, T>()) {
         return false;
     } else {
-        (void)block;
+        constexpr int B = tile_block<N, CT, C, T>();
         if (grad)
-            hipLaunchKernelGGL((k_gather_tiled<N, CT, C, true, T>), dim3(nb), dim3(64), 0, s, ga);
+            hipLaunchKernelGGL((k_gather_tiled<N, CT, C, true, T, B>), dim3(nb), dim3(B), 0, s, ga);
         else
-            hipLaunchKernelGGL((k_gather_tiled<N, CT, C, false, T>), dim3(nb), dim3(64), 0, s, ga);
+            hipLaunchKernelGGL((k_gather_tiled<N, CT, C, false, T, B>), dim3(nb), dim3(B), 0, s, ga);
         return true;
     }
 }
 
 template <int N, typename CT, int C>
-bool launch_tiled_c(int T, const GatherArgs& ga, bool grad, unsigned nb, unsigned block, hipStream_t s) {
+bool launch_tiled_c(int T, const GatherArgs& ga, bool grad, unsigned nb, hipStream_t s) {
     switch (T) {
-        case 4: return launch_tiled_T<N, CT, C, 4>(ga, grad, nb, block, s);
-        case 6: return launch_tiled_T<N, CT, C, 6>(ga, grad, nb, block, s);
-        case 8: return launch_tiled_T<N, CT, C, 8>(ga, grad, nb, block, s);
-        case 10: return launch_tiled_T<N, CT, C, 10>(ga, grad, nb, block, s);
-        case 12: return launch_tiled_T<N, CT, C, 12>(ga, grad, nb, block, s);
-        case 16: return launch_tiled_T<N, CT, C, 16>(ga, grad, nb, block, s);
+        case 4: return launch_tiled_T<N, CT, C, 4>(ga, grad, nb, s);
+        case 6: return launch_tiled_T<N, CT, C, 6>(ga, grad, nb, s);
+        case 8: return launch_tiled_T<N, CT, C, 8>(ga, grad, nb, s);
+        case 12: return launch_tiled_T<N, CT, C, 12>(ga, grad, nb, s);
+        case 16: return launch_tiled_T<N, CT, C, 16>(ga, grad, nb, s);
         default: return false;
     }
 }
 
 template <typename CT>
-bool launch_tiled_ct(int N, int C, int T, const GatherArgs& ga, bool grad, unsigned nb, unsigned block,
-                     hipStream_t s) {
+bool launch_tiled_ct(int N, int C, int T, const GatherArgs& ga, bool grad, unsigned nb, hipStream_t s) {
     if (N == 4)
-        return C == 1 ? launch_tiled_c<4, CT, 1>(T, ga, grad, nb, block, s)
-                      : launch_tiled_c<4, CT, 3>(T, ga, grad, nb, block, s);
-    return C == 1 ? launch_tiled_c<6, CT, 1>(T, ga, grad, nb, block, s)
-                  : launch_tiled_c<6, CT, 3>(T, ga, grad, nb, block, s);
+        return C == 1 ? launch_tiled_c<4, CT, 1>(T, ga, grad, nb, s) : launch_tiled_c<4, CT, 3>(T, ga, grad, nb, s);
+    return C == 1 ? launch_tiled_c<6, CT, 1>(T, ga, grad, nb, s) : launch_tiled_c<6, CT, 3>(T, ga, grad, nb, s);
+}
+
+template <int N, typename CT, int C>
+bool tile_ok_rt(int T) {
+    switch (T) {
+        case 4: return tile_ok<N, CT, C, 4>();
+        case 6: return tile_ok<N, CT, C, 6>();
+        case 8: return tile_ok<N, CT, C, 8>();
+        case 12: return tile_ok<N, CT, C, 12>();
+        case 16: return tile_ok<N, CT, C, 16>();
+        default: return false;
+    }
+}
+
+template <typename CT>
+bool tile_ok_ct(int N, int C, int T) {
+    if (N == 4) return C == 1 ? tile_ok_rt<4, CT, 1>(T) : tile_ok_rt<4, CT, 3>(T);
+    return C == 1 ? tile_ok_rt<6, CT, 1>(T) : tile_ok_rt<6, CT, 3>(T);
 }
 
 }  // namespace
@@ -604,7 +755,7 @@ size_t bin_bucket_count(const bsi_field* f, int tile) {
 
 // Bucket arrays live at the start of the binning scratch: hist[nb], offs[nb], ...
 bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, uint32_t* perm, void* scratch,
-                   hipStream_t s) {
+                   double* pos_sorted, hipStream_t s) {
     const size_t nbf = bin_bucket_count(f, tile);
     const size_t nb = nbf + 1;
     uint32_t* hist = static_cast<uint32_t*>(scratch);
@@ -630,7 +781,8 @@ bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, uint32_t* 
     }
     {
         StageTimer tm(f->ctx, "bin_scatter", s);
-        hipLaunchKernelGGL(k_bin_scatter, dim3(pb), dim3(256), 0, s, P, key, rank, offs, perm);
+        hipLaunchKernelGGL(k_bin_scatter, dim3(pb), dim3(256), 0, s, P, key, rank, offs, perm, pos,
+                           pos_sorted);
     }
     BSI_HIP(hipGetLastError());
     return BSI_OK;
@@ -643,10 +795,9 @@ size_t bin_scratch_bytes(const bsi_field* f, long P, int tile) {
 }
 
 bool tiled_supported(const bsi_field* f, int tile) {
-    const size_t bytes = size_t(tile + f->N - 1) * (tile + f->N - 1) * (tile + f->N - 1) * f->C *
-                         dtype_size(f->desc.coef);
-    const bool listed = tile == 4 || tile == 6 || tile == 8 || tile == 10 || tile == 12 || tile == 16;
-    return listed && bytes <= size_t(TILE_LDS_LIMIT);
+    if (f->desc.coef == BSI_F64) return tile_ok_ct<double>(f->N, f->C, tile);
+    if (f->desc.coef == BSI_F32) return tile_ok_ct<float>(f->N, f->C, tile);
+    return tile_ok_ct<uint16_t>(f->N, f->C, tile);
 }
 
 bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
@@ -656,6 +807,7 @@ bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* g
     BSI_CHECK(block % 64 == 0 && block >= 64 && block <= 256, BSI_E_INVAL,
               "eval block must be 64, 128, 192 or 256");
     const uint32_t* perm = nullptr;
+    const double* pos_sorted = nullptr;
     const uint32_t* hist = nullptr;
     const uint32_t* offs = nullptr;
     int tile = cfg.sort_tile;
@@ -664,12 +816,15 @@ bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* g
         // keep the bucket table at most 2^24 entries
         const int nmax = std::max(f->n[0], std::max(f->n[1], f->n[2]));
         tile = std::max(tile, (nmax + 255) / 256);
-        const size_t need = size_t(P) * sizeof(uint32_t) + bin_scratch_bytes(f, P, tile);
+        const size_t possz = 3 * size_t(P) * sizeof(double);
+        const size_t need = possz + size_t(P) * sizeof(uint32_t) + bin_scratch_bytes(f, P, tile);
         void* ws = nullptr;
         BSI_TRY(get_workspace(f->ctx->eval_ws, s, need, &ws));
-        uint32_t* pm = static_cast<uint32_t*>(ws);
-        BSI_TRY(bin_run(f, pos, P, tile, pm, pm + P, s));
+        double* ps = static_cast<double*>(ws);
+        uint32_t* pm = reinterpret_cast<uint32_t*>(ps + 3 * size_t(P));
+        BSI_TRY(bin_run(f, pos, P, tile, pm, pm + P, ps, s));
         perm = pm;
+        pos_sorted = ps;
         hist = pm + P;
         nbf = bin_bucket_count(f, tile);
         offs = hist + nbf + 1;
@@ -678,6 +833,7 @@ bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* g
     ga.grid = f->grid;
     ga.pos = pos;
     ga.perm = perm;
+    ga.pos_sorted = pos_sorted;
     ga.hist = hist;
     ga.offs = offs;
     ga.u = u;
@@ -689,6 +845,8 @@ bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* g
     ga.n2 = f->n[2];
     ga.P1 = f->P[1];
     ga.P2 = f->P[2];
+    ga.pitch2 = f->pitch2;
+    ga.tiles_per_group = uint32_t(cfg.tiles_per_group > 0 ? cfg.tiles_per_group : 4);
     ga.ih0 = f->inv_h[0];
     ga.ih1 = f->inv_h[1];
     ga.ih2 = f->inv_h[2];
@@ -698,11 +856,11 @@ bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* g
     StageTimer tm(f->ctx, "gather", s);
     const bool tiled = perm && cfg.variant == 0 && tiled_supported(f, tile);
     if (tiled) {
-        const unsigned nb = unsigned(nbf + 1);
+        const unsigned nb = unsigned((nbf + 1 + ga.tiles_per_group - 1) / ga.tiles_per_group);
         bool ok = false;
-        if (f->desc.coef == BSI_F64) ok = launch_tiled_ct<double>(f->N, f->C, tile, ga, g, nb, block, s);
-        else if (f->desc.coef == BSI_F32) ok = launch_tiled_ct<float>(f->N, f->C, tile, ga, g, nb, block, s);
-        else ok = launch_tiled_ct<uint16_t>(f->N, f->C, tile, ga, g, nb, block, s);
+        if (f->desc.coef == BSI_F64) ok = launch_tiled_ct<double>(f->N, f->C, tile, ga, g, nb, s);
+        else if (f->desc.coef == BSI_F32) ok = launch_tiled_ct<float>(f->N, f->C, tile, ga, g, nb, s);
+        else ok = launch_tiled_ct<uint16_t>(f->N, f->C, tile, ga, g, nb, s);
         BSI_CHECK(ok, BSI_E_UNSUPPORTED, "no tiled gather instance for this tile size");
     } else {
         const unsigned nb = unsigned((P + block - 1) / block);

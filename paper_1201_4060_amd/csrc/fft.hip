@@ -244,8 +244,8 @@ struct C2rCfg {
 // tw[m] = exp(+2 pi i m / (2M)), m < 2M.
 template <typename T, typename OutT, int M, int C>
 __global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, OutT* __restrict__ grid,
-                                             int n0, int n1, int P0, int P1, int P2, int padlo,
-                                             const cplx<T>* __restrict__ twg) {
+                                             int n0, int n1, int P0, int P1, int P2, int pitch2,
+                                             int padlo, const cplx<T>* __restrict__ twg) {
     using Cfg = C2rCfg<T, M, C>;
     constexpr int H = M + 1;
     constexpr int LP = M + 2;
@@ -315,10 +315,10 @@ __global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, O
         const int p0b = (p0a - n0 >= 0) ? p0a - n0 : ((p0a + n0 < P0) ? p0a + n0 : -1);
         const int p1a = g1 + padlo;
         const int p1b = (p1a - n1 >= 0) ? p1a - n1 : ((p1a + n1 < P1) ? p1a + n1 : -1);
-        OutT* r_aa = grid + (long(p0a) * P1 + p1a) * rowElems;
-        OutT* r_ab = p1b >= 0 ? grid + (long(p0a) * P1 + p1b) * rowElems : nullptr;
-        OutT* r_ba = p0b >= 0 ? grid + (long(p0b) * P1 + p1a) * rowElems : nullptr;
-        OutT* r_bb = (p0b >= 0 && p1b >= 0) ? grid + (long(p0b) * P1 + p1b) * rowElems : nullptr;
+        OutT* r_aa = grid + (long(p0a) * P1 + p1a) * pitch2;
+        OutT* r_ab = p1b >= 0 ? grid + (long(p0a) * P1 + p1b) * pitch2 : nullptr;
+        OutT* r_ba = p0b >= 0 ? grid + (long(p0b) * P1 + p1a) * pitch2 : nullptr;
+        OutT* r_bb = (p0b >= 0 && p1b >= 0) ? grid + (long(p0b) * P1 + p1b) * pitch2 : nullptr;
         for (int e = tid; e < rowElems; e += Cfg::THREADS) {
             const int p2 = e / C, c = e % C;
             int g2 = p2 - padlo;
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, O
 // Dense FP64 [C][n0][n1][n2] <-> padded interleaved grid.
 template <typename O>
 __global__ void k_from_dense(const double* __restrict__ dense, O* __restrict__ grid, int C, int n0,
-                             int n1, int n2, int P0, int P1, int P2, int padlo) {
+                             int n1, int n2, int P0, int P1, int P2, int pitch2, int padlo) {
     const long total = long(P0) * P1 * P2 * C;
     for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < total;
          i += long(gridDim.x) * blockDim.x) {
@@ -351,12 +351,13 @@ __global__ void k_from_dense(const double* __restrict__ dense, O* __restrict__ g
         g0 += (g0 < 0) ? n0 : (g0 >= n0 ? -n0 : 0);
         g1 += (g1 < 0) ? n1 : (g1 >= n1 ? -n1 : 0);
         g2 += (g2 < 0) ? n2 : (g2 >= n2 ? -n2 : 0);
-        grid[i] = store_cast<O>(dense[((long(c) * n0 + g0) * n1 + g1) * n2 + g2]);
+        grid[(long(p0) * P1 + p1) * pitch2 + long(p2) * C + c] =
+            store_cast<O>(dense[((long(c) * n0 + g0) * n1 + g1) * n2 + g2]);
     }
 }
 template <typename O>
 __global__ void k_to_dense(const O* __restrict__ grid, double* __restrict__ dense, int C, int n0,
-                           int n1, int n2, int P1, int P2, int padlo) {
+                           int n1, int n2, int P1, int pitch2, int padlo) {
     const long total = long(C) * n0 * n1 * n2;
     for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < total;
          i += long(gridDim.x) * blockDim.x) {
@@ -367,7 +368,8 @@ __global__ void k_to_dense(const O* __restrict__ grid, double* __restrict__ dens
         r /= n1;
         const int g0 = int(r % n0);
         const int c = int(r / n0);
-        dense[i] = load_widen<O>(grid[((long(g0 + padlo) * P1 + (g1 + padlo)) * P2 + (g2 + padlo)) * C + c]);
+        dense[i] = load_widen<O>(
+            grid[(long(g0 + padlo) * P1 + (g1 + padlo)) * pitch2 + long(g2 + padlo) * C + c]);
     }
 }
 
@@ -414,14 +416,14 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
 
 template <typename T, typename OutT, int C>
 bsi_status launch_c2r(int M, const cplx<T>* work, OutT* grid, int n0, int n1, int P0, int P1, int P2,
-                      int padlo, const cplx<T>* tw, hipStream_t s) {
+                      int pitch2, int padlo, const cplx<T>* tw, hipStream_t s) {
     const long nlines = long(n0) * n1;
 #define BSI_C2R_CASE(MM)                                                                           \
     case MM: {                                                                                     \
         using Cfg = C2rCfg<T, MM, C>;                                                                 \
         const unsigned nb = unsigned((nlines + Cfg::LINES - 1) / Cfg::LINES);                      \
         hipLaunchKernelGGL((k_c2r<T, OutT, MM, C>), dim3(nb), dim3(Cfg::THREADS), 0, s, work, grid, \
-                           n0, n1, P0, P1, P2, padlo, tw);                                         \
+                           n0, n1, P0, P1, P2, pitch2, padlo, tw);                                 \
         break;                                                                                     \
     }
     switch (M) {
@@ -486,9 +488,9 @@ bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_
     const int M = n2 / 2;
     StageTimer tm(ctx, "fft_c2r", s);
     if (C == 1)
-        return launch_c2r<T, OutT, 1>(M, work, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->padlo,
+        return launch_c2r<T, OutT, 1>(M, work, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, f->padlo,
                                       static_cast<const cplx<T>*>(tw2), s);
-    return launch_c2r<T, OutT, 3>(M, work, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->padlo,
+    return launch_c2r<T, OutT, 3>(M, work, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, f->padlo,
                                   static_cast<const cplx<T>*>(tw2), s);
 }
 
@@ -523,15 +525,15 @@ bsi_status grid_from_dense(bsi_field* f, const double* dense, hipStream_t s) {
     if (f->desc.coef == BSI_F64)
         hipLaunchKernelGGL(k_from_dense<double>, dim3(nb), dim3(256), 0, s, dense,
                            static_cast<double*>(f->grid), f->C, f->n[0], f->n[1], f->n[2], f->P[0],
-                           f->P[1], f->P[2], f->padlo);
+                           f->P[1], f->P[2], f->pitch2, f->padlo);
     else if (f->desc.coef == BSI_F32)
         hipLaunchKernelGGL(k_from_dense<float>, dim3(nb), dim3(256), 0, s, dense,
                            static_cast<float*>(f->grid), f->C, f->n[0], f->n[1], f->n[2], f->P[0],
-                           f->P[1], f->P[2], f->padlo);
+                           f->P[1], f->P[2], f->pitch2, f->padlo);
     else
         hipLaunchKernelGGL(k_from_dense<uint16_t>, dim3(nb), dim3(256), 0, s, dense,
                            static_cast<uint16_t*>(f->grid), f->C, f->n[0], f->n[1], f->n[2], f->P[0],
-                           f->P[1], f->P[2], f->padlo);
+                           f->P[1], f->P[2], f->pitch2, f->padlo);
     BSI_HIP(hipGetLastError());
     return BSI_OK;
 }
@@ -542,15 +544,15 @@ bsi_status grid_to_dense(const bsi_field* f, double* dense, hipStream_t s) {
     if (f->desc.coef == BSI_F64)
         hipLaunchKernelGGL(k_to_dense<double>, dim3(nb), dim3(256), 0, s,
                            static_cast<const double*>(f->grid), dense, f->C, f->n[0], f->n[1], f->n[2],
-                           f->P[1], f->P[2], f->padlo);
+                           f->P[1], f->pitch2, f->padlo);
     else if (f->desc.coef == BSI_F32)
         hipLaunchKernelGGL(k_to_dense<float>, dim3(nb), dim3(256), 0, s,
                            static_cast<const float*>(f->grid), dense, f->C, f->n[0], f->n[1], f->n[2],
-                           f->P[1], f->P[2], f->padlo);
+                           f->P[1], f->pitch2, f->padlo);
     else
         hipLaunchKernelGGL(k_to_dense<uint16_t>, dim3(nb), dim3(256), 0, s,
                            static_cast<const uint16_t*>(f->grid), dense, f->C, f->n[0], f->n[1],
-                           f->n[2], f->P[1], f->P[2], f->padlo);
+                           f->n[2], f->P[1], f->pitch2, f->padlo);
     BSI_HIP(hipGetLastError());
     return BSI_OK;
 }
