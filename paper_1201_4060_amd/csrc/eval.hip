@@ -686,7 +686,7 @@ constexpr bool tile_ok() {
 // 64 threads for small tiles, 256 for tiles whose block fills the LDS budget
 template <int N, typename CT, int C, int T>
 constexpr int tile_block() {
-    return TileGeom<N, CT, C, T>::SLOTS >= 1536 ? 256 : 64;
+    return TileGeom<N, CT, C, T>::SLOTS >= 3072 ? 256 : 64;
 }
 
 template <int N, typename CT, int C, int T>
