@@ -18,6 +18,11 @@
 // consecutive elements.
 #include "common.hpp"
 
+// LDS budget (KiB) of one strided-pass workgroup's line block
+#ifndef BSI_FFT_LDS_KB
+#define BSI_FFT_LDS_KB 68
+#endif
+
 namespace bsi {
 
 template <typename T>
@@ -129,15 +134,25 @@ __device__ __forceinline__ void fft_stages(cplx<T>* buf, const cplx<T>* tw, int 
 }
 
 // Lines per workgroup for the strided passes: keep the LDS line block near 33 KB.
-// W lines per workgroup, TEAM threads per line; TEAM divides LEN so that each
-// thread moves a fixed line and a fixed set of rows.
+// W lines per workgroup (longer contiguous row segments of the strided axis
+// are better for HBM), TEAM threads per line; TEAM divides LEN so that each
+// thread moves a fixed line and a fixed set of rows.  The line block plus the
+// twiddle table stay within BSI_FFT_LDS_KB.
+#ifndef BSI_FFT_WMAX
+#define BSI_FFT_WMAX 32
+#endif
+#ifndef BSI_FFT_THREADS
+#define BSI_FFT_THREADS 512
+#endif
 template <typename T, int LEN>
 struct StridedCfg {
     static constexpr int bytes = int(sizeof(cplx<T>));
-    static constexpr int raw = (33 * 1024) / ((LEN + 1) * bytes);
-    static constexpr int W = raw >= 16 ? 16 : raw >= 8 ? 8 : raw >= 4 ? 4 : 2;
+    static constexpr int raw = (BSI_FFT_LDS_KB * 1024 - LEN * bytes) / ((LEN + 1) * bytes);
+    static constexpr int W = raw >= 32 && BSI_FFT_WMAX >= 32 ? 32
+                             : raw >= 16 && BSI_FFT_WMAX >= 16 ? 16
+                             : raw >= 8 ? 8 : raw >= 4 ? 4 : 2;
     static constexpr int POW2 = LEN & (-LEN);  // largest power of two dividing LEN
-    static constexpr int TEAM = (256 / W) < POW2 ? (256 / W) : POW2;
+    static constexpr int TEAM = (BSI_FFT_THREADS / W) < POW2 ? (BSI_FFT_THREADS / W) : POW2;
     static constexpr int THREADS = W * TEAM;
 };
 
@@ -147,7 +162,7 @@ struct StridedCfg {
 // symbol cAxis[a] * cOther[other] * c2[k2]; otherwise in-place on the work
 // buffer (in == out).
 template <typename T, typename InT, int LEN, bool FIRST>
-__global__ __launch_bounds__(256) void k_fft_axis(const InT* in, cplx<T>* out, int H, long sAxis,
+__global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cplx<T>* out, int H, long sAxis,
                                                   long sOther, long sComp, const double* cAxis,
                                                   const double* cOther, const double* c2,
                                                   const cplx<T>* twg) {
