@@ -133,3 +133,13 @@ def test_bspline_integer_samples():
     assert [bspline_exact(4, k) for k in (0, 1, 2)] == [Fraction(2, 3), Fraction(1, 6), 0]
     assert [bspline_exact(6, k) for k in (0, 1, 2, 3)] == \
         [Fraction(11, 20), Fraction(13, 60), Fraction(1, 120), 0]
+
+
+@pytest.mark.parametrize("N,want", [(4, Fraction(3, 2)), (6, Fraction(115, 96))])
+def test_derivative_weight_l1_at_half(N, want):
+    # sum_j |w'_j(t)| is largest at t = 1/2 (used to bound BF16 storage error
+    # of the gradient); exact value there and not exceeded on a fine grid
+    M1 = derivative_matrix(bspline_matrix(N), 1)
+    l1 = lambda t: sum(abs(_poly(M1[j], t)) for j in range(N))
+    assert l1(Fraction(1, 2)) == want
+    assert all(l1(Fraction(k, 200)) <= want for k in range(201))
