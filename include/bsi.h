@@ -146,7 +146,8 @@ bsi_status bsi_field_get_coefficients(const bsi_field* field, double* grid_dev,
  * pointers, 8-byte aligned.  0 <= P < 2^31; P == 0 does nothing. */
 bsi_status bsi_eval(bsi_field* field, const double* pos_dev, int64_t P,
                     void* u_dev, void* grad_dev, void* hip_stream);
-/* Same with explicit tuning knobs (NULL = the context's tuned defaults). */
+/* Same with explicit tuning knobs (NULL = the context's tuned configuration
+ * for this field and particle count, see bsi_ctx_lookup_config). */
 bsi_status bsi_eval_ex(bsi_field* field, const double* pos_dev, int64_t P,
                        void* u_dev, void* grad_dev, const bsi_eval_config* cfg,
                        void* hip_stream);
@@ -162,13 +163,88 @@ bsi_status bsi_debug_cells(bsi_field* field, const double* pos_dev, int64_t P,
  * (synchronises the field's last stream). */
 bsi_status bsi_field_stats(bsi_field* field, int64_t* nonfinite_positions);
 
+/* ---- batching: many fields in one persistent launch ----------------------- */
+
+/* One evaluation inside a batch: the arguments of bsi_eval for one field. */
+typedef struct bsi_eval_item {
+    bsi_field* field;
+    const double* pos;   /* device, FP64 [P][3]                        */
+    int64_t P;           /* 0 <= P < 2^31; an item with P == 0 is skipped */
+    void* u;             /* device, [P][ncomp]                         */
+    void* grad;          /* device, [P][ncomp][3], or NULL (checked on items with P > 0) */
+} bsi_eval_item;
+
+typedef struct bsi_batch bsi_batch;
+
+/* Plan the evaluation of `count` items (1..65535) as one unit of work: every
+ * item's particles are binned by the Morton tile of its own sort granularity,
+ * and one persistent gather kernel walks a shared work list -- the non-empty
+ * tiles of the items gathered from LDS tiles (4^3 or 8^3 cells) and groups of
+ * 64 binned particles of the items gathered one lane per particle -- so that
+ * large and small items share the GPU without a launch per item.  cfgs (count
+ * entries) gives each item's configuration, or NULL for the tuned ones
+ * (bsi_ctx_lookup_config); a tiled configuration whose tile the batch kernel
+ * lacks uses the nearest of 4 and 8.  Results are bitwise those of
+ * bsi_eval_ex with the item's planned configuration (bsi_batch_item_config).
+ * All items belong to `ctx`, share the coefficient type, and give grad for
+ * all items or for none (BSI_E_INVAL otherwise).  The batch owns a device
+ * workspace sized for the items; the item pointers are fixed at creation (new
+ * particles are evaluated by writing them into the same buffers).
+ * BSI_E_NOMEM if the workspace does not fit. */
+bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t count,
+                            const bsi_eval_config* cfgs, bsi_batch** out);
+/* Run the batch on `hip_stream`.  use_graph = 0 enqueues the kernels
+ * directly; use_graph = 1 captures them into a HIP graph on the first call
+ * (no memset nodes: counters are cleared by a kernel) and launches that graph
+ * on every call. */
+bsi_status bsi_batch_run(bsi_batch* batch, int32_t use_graph, void* hip_stream);
+/* The configuration item `item` is evaluated with (variant 0 = tiled with
+ * sort_tile 4 or 8, variant 1 = one lane per particle binned by sort_tile). */
+bsi_status bsi_batch_item_config(const bsi_batch* batch, int32_t item, bsi_eval_config* cfg);
+/* Device bytes of the batch workspace. */
+size_t bsi_batch_bytes(const bsi_batch* batch);
+/* Wait for the device, then free the batch and its graph. */
+void bsi_batch_destroy(bsi_batch* batch);
+/* One-shot: create, run without a graph, synchronise `hip_stream`, destroy. */
+bsi_status bsi_eval_batch(bsi_ctx* ctx, const bsi_eval_item* items, int32_t count, void* hip_stream);
+
+/* ---- autotuning ------------------------------------------------------------- */
+
+/* Time the candidate configurations of the evaluation (LDS-tiled gather with
+ * sort tiles 4, 6, 8, 12, 16 and 1, 2, 4 tiles per workgroup; one lane per
+ * particle binned by 4, 8, 16, 32) on P uniform positions generated on the
+ * device from `seed`, and keep the fastest in the context's table under
+ * (order, coefficient type, ncomp, density class round(log2(P / n0 n1 n2))).
+ * When db_path is not NULL the entry is appended to that JSON-lines file.
+ * best / best_us (may be NULL) receive the winner and its median time in
+ * microseconds.  Allocates and frees its own buffers; synchronises. */
+bsi_status bsi_tune(bsi_field* field, int64_t P, uint64_t seed, const char* db_path,
+                    bsi_eval_config* best, double* best_us);
+/* Add the entries of a JSON-lines file written by bsi_tune to the context's
+ * table (later entries replace earlier ones with the same key).  BSI_E_INVAL
+ * for an unreadable file or a malformed entry (nothing is added then). */
+bsi_status bsi_ctx_load_tuning(bsi_ctx* ctx, const char* db_path);
+/* The configuration bsi_eval and the batch planner use for `field` and P
+ * particles: the table entry of the same key, else the nearest density class
+ * (at most two away) of the same order/type/ncomp, else the built-in default
+ * (tiled with 8^3-cell tiles from 1/64 particles per cell up, one lane per
+ * particle below). */
+bsi_status bsi_ctx_lookup_config(bsi_ctx* ctx, const bsi_field* field, int64_t P, bsi_eval_config* out);
+/* Write P uniform positions in [0,L0)x[0,L1)x[0,L2) (length[3]) to pos_dev
+ * [P][3]: coordinate d of particle p is L_d * u(3p + d), u(i) the top 53 bits
+ * of SplitMix64 output i of `seed` (Steele, Lea and Flood 2014) over 2^53.
+ * Used for tuning and for load generation. */
+bsi_status bsi_fill_uniform_positions(bsi_ctx* ctx, uint64_t seed, int64_t P, const double* length,
+                                      double* pos_dev, void* hip_stream);
+
 /* ---- stage timing -------------------------------------------------------- */
 
 /* Enable (1) or disable (0) per-stage timing on a context.  While enabled, the
  * library brackets each of its kernel launches with HIP events recorded on the
  * launch stream, so durations are those of the kernels themselves.  Stages:
  * "fft_axis0", "fft_axis1", "fft_c2r", "bin_count", "bin_scan", "bin_scatter",
- * "gather", "batch_gather". */
+ * "gather"; batches: "batch_bin", "batch_gather" (direct runs) and
+ * "batch_graph" (graph launches).  Nothing is timed inside a stream capture. */
 bsi_status bsi_ctx_set_timing(bsi_ctx* ctx, int32_t enabled);
 /* Total milliseconds and number of launches recorded for `stage` since the
  * last reset (waits for the recorded events). */

@@ -78,6 +78,18 @@ SIGNATURES = {
     "bsi_ctx_read_timing": (ST, [VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(I64)]),
     "bsi_ctx_reset_timing": (ST, [VP]),
+    "bsi_batch_create": (ST, [VP, ctypes.POINTER(EvalItem), I32, ctypes.POINTER(EvalConfig),
+                              ctypes.POINTER(VP)]),
+    "bsi_batch_run": (ST, [VP, I32, VP]),
+    "bsi_batch_item_config": (ST, [VP, I32, ctypes.POINTER(EvalConfig)]),
+    "bsi_batch_bytes": (ctypes.c_size_t, [VP]),
+    "bsi_batch_destroy": (None, [VP]),
+    "bsi_eval_batch": (ST, [VP, ctypes.POINTER(EvalItem), I32, VP]),
+    "bsi_tune": (ST, [VP, I64, ctypes.c_uint64, ctypes.c_char_p, ctypes.POINTER(EvalConfig),
+                      ctypes.POINTER(ctypes.c_double)]),
+    "bsi_ctx_load_tuning": (ST, [VP, ctypes.c_char_p]),
+    "bsi_ctx_lookup_config": (ST, [VP, VP, I64, ctypes.POINTER(EvalConfig)]),
+    "bsi_fill_uniform_positions": (ST, [VP, ctypes.c_uint64, I64, ctypes.POINTER(ctypes.c_double), VP, VP]),
 }
 
 
@@ -201,3 +213,69 @@ def bsi_ctx_read_timing(ctx, stage):
 
 def bsi_ctx_reset_timing(ctx):
     _check(lib().bsi_ctx_reset_timing(ctx), "bsi_ctx_reset_timing")
+
+
+def make_items(items):
+    """[(field, pos, P, u, grad)] -> ctypes array of EvalItem."""
+    arr = (EvalItem * len(items))()
+    for i, (field, pos, P, u, grad) in enumerate(items):
+        arr[i].field, arr[i].pos, arr[i].P = field, _ptr(pos), P
+        arr[i].u, arr[i].grad = _ptr(u), _ptr(grad)
+    return arr
+
+
+def bsi_batch_create(ctx, items, cfgs=None):
+    arr = make_items(items)
+    c = None
+    if cfgs is not None:
+        c = (EvalConfig * len(items))(*cfgs)
+    out = VP()
+    _check(lib().bsi_batch_create(ctx, arr, len(items), c, ctypes.byref(out)), "bsi_batch_create")
+    return out.value
+
+
+def bsi_batch_run(batch, use_graph=False, stream=None):
+    _check(lib().bsi_batch_run(batch, 1 if use_graph else 0, stream), "bsi_batch_run")
+
+
+def bsi_batch_item_config(batch, item):
+    c = EvalConfig()
+    _check(lib().bsi_batch_item_config(batch, item, ctypes.byref(c)), "bsi_batch_item_config")
+    return c
+
+
+def bsi_batch_bytes(batch):
+    return lib().bsi_batch_bytes(batch)
+
+
+def bsi_batch_destroy(batch):
+    lib().bsi_batch_destroy(batch)
+
+
+def bsi_eval_batch(ctx, items, stream=None):
+    arr = make_items(items)
+    _check(lib().bsi_eval_batch(ctx, arr, len(items), stream), "bsi_eval_batch")
+
+
+def bsi_tune(field, P, seed=0, db_path=None):
+    c = EvalConfig()
+    us = ctypes.c_double()
+    _check(lib().bsi_tune(field, P, seed, db_path.encode() if db_path else None, ctypes.byref(c),
+                          ctypes.byref(us)), "bsi_tune")
+    return c, us.value
+
+
+def bsi_ctx_load_tuning(ctx, db_path):
+    _check(lib().bsi_ctx_load_tuning(ctx, db_path.encode()), "bsi_ctx_load_tuning")
+
+
+def bsi_ctx_lookup_config(ctx, field, P):
+    c = EvalConfig()
+    _check(lib().bsi_ctx_lookup_config(ctx, field, P, ctypes.byref(c)), "bsi_ctx_lookup_config")
+    return c
+
+
+def bsi_fill_uniform_positions(ctx, seed, P, length, pos, stream=None):
+    L = (ctypes.c_double * 3)(*length)
+    _check(lib().bsi_fill_uniform_positions(ctx, seed, P, L, _ptr(pos), stream),
+           "bsi_fill_uniform_positions")

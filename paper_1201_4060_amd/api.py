@@ -108,3 +108,47 @@ class Field:
 
     def nonfinite_count(self):
         return _bsi.bsi_field_stats(self.handle)
+
+
+class Batch:
+    """bsi_batch: evaluations of several fields run by one persistent gather.
+
+    items: list of (field, pos, u, grad) with device tensors (grad may be None
+    for every item).  cfgs: optional list of EvalConfig, one per item.  The
+    tensors must stay alive and in place while the batch exists.
+    """
+
+    def __init__(self, ctx, items, cfgs=None):
+        self.ctx = ctx
+        self._keep = items
+        raw = []
+        for field, pos, u, grad in items:
+            assert pos.is_cuda and pos.is_contiguous() and pos.dtype == torch.float64
+            assert pos.dim() == 2 and pos.shape[1] == 3
+            P = pos.shape[0]
+            assert u.shape == (P, field.ncomp) and u.dtype == field.out_dtype and u.is_contiguous()
+            if grad is not None:
+                assert grad.shape == (P, field.ncomp, 3) and grad.dtype == field.out_dtype
+                assert grad.is_contiguous()
+            raw.append((field.handle, pos, P, u, grad))
+        self.handle = _bsi.bsi_batch_create(ctx.handle, raw, cfgs)
+
+    def run(self, use_graph=False):
+        _bsi.bsi_batch_run(self.handle, use_graph, _stream())
+
+    def item_config(self, i):
+        return _bsi.bsi_batch_item_config(self.handle, i)
+
+    def nbytes(self):
+        return _bsi.bsi_batch_bytes(self.handle)
+
+    def close(self):
+        if self.handle:
+            _bsi.bsi_batch_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -17,6 +17,13 @@ void clear_error() { g_last_error.clear(); }
 
 StageTimer::StageTimer(bsi_ctx* ctx, const char* stage, hipStream_t s) : ctx_(ctx), stage_(stage), s_(s) {
     if (!ctx_ || !ctx_->timing) return;
+    // no timing inside a stream capture (the events would belong to the graph)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s_, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    if (cs != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> lk(ctx_->mu);
     if (!ctx_->event_pool.empty()) {
         start_ = ctx_->event_pool.back();
@@ -177,6 +184,8 @@ bsi_status check_device_ptr(const void* p, const char* what) {
 
 }  // namespace
 
+bsi_status check_device_ptr_ex(const void* p, const char* what) { return check_device_ptr(p, what); }
+
 }  // namespace bsi
 
 using namespace bsi;
@@ -203,11 +212,6 @@ bsi_status bsi_ctx_create(int device, void* hip_stream, bsi_ctx** out) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     ctx->num_cus = prop.multiProcessorCount;
     ctx->lds_per_block = prop.sharedMemPerBlock;
-    ctx->tuned.sort_tile = 8;
-    ctx->tuned.block = 256;
-    ctx->tuned.xcd_remap = 1;
-    ctx->tuned.variant = 0;
-    ctx->tuned.tiles_per_group = 2;
     *out = ctx;
     return BSI_OK;
 }
@@ -378,7 +382,9 @@ bsi_status bsi_eval_ex(bsi_field* f, const double* pos, int64_t P, void* u, void
     BSI_HIP(hipSetDevice(f->ctx->device));
     hipStream_t s = pick_stream(f->ctx, stream);
     f->last_stream = s;
-    const bsi_eval_config c = cfg ? *cfg : f->ctx->tuned;
+    bsi_eval_config c{};
+    if (cfg) c = *cfg;
+    else BSI_TRY(lookup_config(f->ctx, f, P, &c));
     BSI_CHECK(c.sort_tile >= 0 && c.sort_tile <= 1024, BSI_E_INVAL, "sort_tile out of range");
     return eval_run(f, pos, P, u, grad, c, s);
 }

@@ -1,0 +1,583 @@
+// Batched evaluation: many fields with uneven particle sets evaluated by one
+// persistent gather launch, optionally captured once into a HIP graph and
+// replayed.  The per-particle arithmetic is the single-field one
+// (gather.hpp), so every item's result is bitwise the result of bsi_eval_ex
+// with the same configuration.
+//
+// Plan (host, at creation): items are laid end to end in one particle index
+// space and one bucket index space.  Each item is binned by the Morton tile of
+// its own sort granularity; the tuned (or given) configuration decides per
+// item whether its particles are gathered tile by tile from LDS (tiles of 4^3
+// or 8^3 cells) or one lane per particle from global memory.
+//
+// Device work (one stream, no host synchronisation in between):
+//   fill        zero the bucket histogram and the two work counters
+//   bin_count   cell and Morton bucket of every particle (all items at once)
+//   scan        exclusive scan of the histogram -> binned offsets
+//   bin_scatter binned permutation and binned copy of the positions
+//   compact     list of the non-empty buckets of the tiled items
+//   gather      persistent: each workgroup (one wavefront) takes the next unit
+//               of work -- a non-empty tile of a tiled item, or 64 consecutive
+//               binned particles of a direct item -- from a global counter
+//               until none is left.
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "gather.hpp"
+
+namespace bsi {
+
+namespace {
+
+constexpr int BATCH_B = 64;        // threads per workgroup of the persistent gather
+constexpr int BLK = 256;           // threads per workgroup of the binning kernels
+enum : int32_t { MODE_DIRECT = 0, MODE_TILE4 = 1, MODE_TILE8 = 2 };
+
+struct BatchItem {
+    GatherArgs ga;       // hist/offs at the item's buckets; perm/pos_sorted are the batch-wide arrays
+    int32_t N, C, mode, tile;
+    uint32_t pbase;      // first particle slot of the item in the batch
+    uint32_t bbase;      // first bucket of the item in the batch
+    uint32_t nb;         // buckets of the item, the non-finite bucket included
+    uint32_t pblk;       // first binning workgroup of the item
+    uint32_t bblk;       // first compaction workgroup of the item (tiled items)
+    uint32_t ubase;      // first direct unit of the item (direct items)
+};
+
+struct BatchArgs {
+    const BatchItem* items;
+    const uint16_t* pblock_item;  // item of each binning workgroup
+    const uint16_t* bblock_item;  // item of each compaction workgroup
+    const uint16_t* dunit_item;   // item of each direct unit
+    uint32_t* hist;
+    uint32_t* offs;
+    uint32_t* key;
+    uint32_t* rank;
+    uint32_t* perm;
+    double* pos_sorted;
+    uint2* tile_list;             // (item, bucket) of every non-empty tile
+    uint32_t* ctr;                // [0] next unit, [1] number of tile units
+    uint32_t ndirect;
+};
+
+// cell -> item-local Morton bucket, or the item's non-finite bucket
+__device__ __forceinline__ uint32_t item_bucket(const BatchItem& it, const double* x) {
+    const int n[3] = {it.ga.n0, it.ga.n1, it.ga.n2};
+    const double ih[3] = {it.ga.ih0, it.ga.ih1, it.ga.ih2};
+    int c[3];
+    double t[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ok = cell_of(x[d], ih[d], n[d], c[d], t[d]) && ok;
+    if (!ok) return it.nb - 1;
+    const uint32_t T = uint32_t(it.tile);
+    return (spread3(uint32_t(c[0]) / T) << 2) | (spread3(uint32_t(c[1]) / T) << 1) |
+           spread3(uint32_t(c[2]) / T);
+}
+
+__global__ __launch_bounds__(BLK) void k_batch_bin_count(BatchArgs b) {
+    const BatchItem& it = b.items[b.pblock_item[blockIdx.x]];
+    const long p = long(blockIdx.x - it.pblk) * BLK + threadIdx.x;
+    if (p >= it.ga.P) return;
+    const double x[3] = {it.ga.pos[3 * p], it.ga.pos[3 * p + 1], it.ga.pos[3 * p + 2]};
+    const uint32_t k = it.bbase + item_bucket(it, x);
+    const long g = long(it.pbase) + p;
+    b.key[g] = k;
+    b.rank[g] = atomicAdd(&b.hist[k], 1u);
+}
+
+__global__ __launch_bounds__(BLK) void k_batch_bin_scatter(BatchArgs b) {
+    const BatchItem& it = b.items[b.pblock_item[blockIdx.x]];
+    const long p = long(blockIdx.x - it.pblk) * BLK + threadIdx.x;
+    if (p >= it.ga.P) return;
+    const long g = long(it.pbase) + p;
+    const uint32_t dst = b.offs[b.key[g]] + b.rank[g];
+    b.perm[dst] = uint32_t(p);
+    const double x0 = it.ga.pos[3 * p], x1 = it.ga.pos[3 * p + 1], x2 = it.ga.pos[3 * p + 2];
+    b.pos_sorted[3 * long(dst)] = x0;
+    b.pos_sorted[3 * long(dst) + 1] = x1;
+    b.pos_sorted[3 * long(dst) + 2] = x2;
+}
+
+__global__ __launch_bounds__(BLK) void k_batch_compact(BatchArgs b) {
+    const uint32_t item = b.bblock_item[blockIdx.x];
+    const BatchItem& it = b.items[item];
+    const uint32_t k = (blockIdx.x - it.bblk) * BLK + threadIdx.x;
+    if (k >= it.nb) return;
+    if (b.hist[it.bbase + k] != 0u) b.tile_list[atomicAdd(&b.ctr[1], 1u)] = make_uint2(item, k);
+}
+
+template <int N, typename CT, int C, int T>
+constexpr bool batch_tile_ok() {
+    return TileGeom<N, CT, C, T>::BYTES <= 65536 && TileGeom<N, CT, C, T>::ALIGNED &&
+           TileGeom<N, CT, C, T>::SLOTS < 3072;
+}
+
+template <int N, typename CT, int C, bool GRAD>
+__device__ __forceinline__ void batch_tile(const GatherArgs& a, int mode, uint32_t bucket, u32x4* lds) {
+    if (mode == MODE_TILE8) {
+        if constexpr (batch_tile_ok<N, CT, C, 8>()) tile_eval<N, CT, C, GRAD, 8, BATCH_B>(a, bucket, lds);
+    } else {
+        if constexpr (batch_tile_ok<N, CT, C, 4>()) tile_eval<N, CT, C, GRAD, 4, BATCH_B>(a, bucket, lds);
+    }
+}
+
+template <typename CT, bool GRAD>
+__global__ __launch_bounds__(BATCH_B) void k_batch_gather(BatchArgs b) {
+    extern __shared__ u32x4 lds[];
+    const uint32_t ntile = b.ctr[1];
+    const uint32_t total = ntile + b.ndirect;
+    for (;;) {
+        uint32_t u = 0;
+        if (threadIdx.x == 0) u = atomicAdd(&b.ctr[0], 1u);
+        u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, 64));
+        if (u >= total) break;
+        // everything that selects a code path is made wave-uniform explicitly,
+        // so that the class switch is a scalar branch
+        if (u < ntile) {
+            const uint2 e = b.tile_list[u];
+            const uint32_t item = __builtin_amdgcn_readfirstlane(e.x);
+            const uint32_t bucket = __builtin_amdgcn_readfirstlane(e.y);
+            const BatchItem& it = b.items[item];
+            const int key = __builtin_amdgcn_readfirstlane(it.N * 2 + (it.C == 3 ? 1 : 0));
+            const int mode = __builtin_amdgcn_readfirstlane(it.mode);
+            switch (key) {
+                case 8: batch_tile<4, CT, 1, GRAD>(it.ga, mode, bucket, lds); break;
+                case 9: batch_tile<4, CT, 3, GRAD>(it.ga, mode, bucket, lds); break;
+                case 12: batch_tile<6, CT, 1, GRAD>(it.ga, mode, bucket, lds); break;
+                default: batch_tile<6, CT, 3, GRAD>(it.ga, mode, bucket, lds); break;
+            }
+        } else {
+            const uint32_t d = u - ntile;
+            const uint32_t item = __builtin_amdgcn_readfirstlane(uint32_t(b.dunit_item[d]));
+            const BatchItem& it = b.items[item];
+            const long r = long(d - it.ubase) * BATCH_B + threadIdx.x;
+            if (r < it.ga.P) {
+                const long j = long(it.pbase) + r;
+                const int key = __builtin_amdgcn_readfirstlane(it.N * 2 + (it.C == 3 ? 1 : 0));
+                switch (key) {
+                    case 8: direct_eval<4, CT, 1, GRAD>(it.ga, j); break;
+                    case 9: direct_eval<4, CT, 3, GRAD>(it.ga, j); break;
+                    case 12: direct_eval<6, CT, 1, GRAD>(it.ga, j); break;
+                    default: direct_eval<6, CT, 3, GRAD>(it.ga, j); break;
+                }
+            }
+        }
+    }
+}
+
+template <typename CT>
+bool tile_supported_batch(int N, int C, int T) {
+    if (T != 4 && T != 8) return false;
+    if (N == 4) {
+        if (C == 1) return T == 4 ? batch_tile_ok<4, CT, 1, 4>() : batch_tile_ok<4, CT, 1, 8>();
+        return T == 4 ? batch_tile_ok<4, CT, 3, 4>() : batch_tile_ok<4, CT, 3, 8>();
+    }
+    if (C == 1) return T == 4 ? batch_tile_ok<6, CT, 1, 4>() : batch_tile_ok<6, CT, 1, 8>();
+    return T == 4 ? batch_tile_ok<6, CT, 3, 4>() : batch_tile_ok<6, CT, 3, 8>();
+}
+
+bool batch_tile_supported(int coef, int N, int C, int T) {
+    if (coef == BSI_F64) return tile_supported_batch<double>(N, C, T);
+    if (coef == BSI_F32) return tile_supported_batch<float>(N, C, T);
+    return tile_supported_batch<uint16_t>(N, C, T);
+}
+
+template <typename CT>
+int tile_lds_ct(int N, int C, int T) {
+    auto one = [&](auto n_, auto c_, auto t_) -> int {
+        constexpr int n = decltype(n_)::value, c = decltype(c_)::value, t = decltype(t_)::value;
+        return tile_lds_bytes<n, CT, c, t, BATCH_B>();
+    };
+    using I4 = std::integral_constant<int, 4>;
+    using I6 = std::integral_constant<int, 6>;
+    using I1 = std::integral_constant<int, 1>;
+    using I3 = std::integral_constant<int, 3>;
+    using I8 = std::integral_constant<int, 8>;
+    if (N == 4) {
+        if (C == 1) return T == 4 ? one(I4{}, I1{}, I4{}) : one(I4{}, I1{}, I8{});
+        return T == 4 ? one(I4{}, I3{}, I4{}) : one(I4{}, I3{}, I8{});
+    }
+    if (C == 1) return T == 4 ? one(I6{}, I1{}, I4{}) : one(I6{}, I1{}, I8{});
+    return T == 4 ? one(I6{}, I3{}, I4{}) : one(I6{}, I3{}, I8{});
+}
+
+int batch_tile_lds(int coef, int N, int C, int T) {
+    if (coef == BSI_F64) return tile_lds_ct<double>(N, C, T);
+    if (coef == BSI_F32) return tile_lds_ct<float>(N, C, T);
+    return tile_lds_ct<uint16_t>(N, C, T);
+}
+
+const void* gather_kernel(int coef, bool grad) {
+    if (coef == BSI_F64)
+        return grad ? reinterpret_cast<const void*>(&k_batch_gather<double, true>)
+                    : reinterpret_cast<const void*>(&k_batch_gather<double, false>);
+    if (coef == BSI_F32)
+        return grad ? reinterpret_cast<const void*>(&k_batch_gather<float, true>)
+                    : reinterpret_cast<const void*>(&k_batch_gather<float, false>);
+    return grad ? reinterpret_cast<const void*>(&k_batch_gather<uint16_t, true>)
+                : reinterpret_cast<const void*>(&k_batch_gather<uint16_t, false>);
+}
+
+void launch_gather(int coef, bool grad, unsigned grid, size_t lds, hipStream_t s, const BatchArgs& a) {
+    if (coef == BSI_F64) {
+        if (grad) hipLaunchKernelGGL((k_batch_gather<double, true>), dim3(grid), dim3(BATCH_B), lds, s, a);
+        else hipLaunchKernelGGL((k_batch_gather<double, false>), dim3(grid), dim3(BATCH_B), lds, s, a);
+    } else if (coef == BSI_F32) {
+        if (grad) hipLaunchKernelGGL((k_batch_gather<float, true>), dim3(grid), dim3(BATCH_B), lds, s, a);
+        else hipLaunchKernelGGL((k_batch_gather<float, false>), dim3(grid), dim3(BATCH_B), lds, s, a);
+    } else {
+        if (grad) hipLaunchKernelGGL((k_batch_gather<uint16_t, true>), dim3(grid), dim3(BATCH_B), lds, s, a);
+        else hipLaunchKernelGGL((k_batch_gather<uint16_t, false>), dim3(grid), dim3(BATCH_B), lds, s, a);
+    }
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+}  // namespace bsi
+
+using namespace bsi;
+
+struct bsi_batch {
+    bsi_ctx* ctx = nullptr;
+    std::vector<bsi_eval_config> cfgs;   // per item, as planned
+    int coef = BSI_F32;
+    bool grad = true;
+    int nitems = 0;                      // items with P > 0
+    uint64_t Ptot = 0, Btot = 0;
+    uint32_t npblocks = 0, nbblocks = 0, ndirect = 0;
+    size_t nsums = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    BatchArgs args{};
+    unsigned grid = 0;
+    size_t lds = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace bsi {
+
+// Plan choice of one item from a configuration: a tiled configuration keeps
+// the tiled gather with the batch kernel's tile nearest to its sort tile (4 up
+// to 6 cells, else 8; the other one if that one does not fit); anything else
+// is gathered one lane per particle, binned with the configuration's tile.
+static void item_mode(const bsi_field* f, const bsi_eval_config& c, int* mode, int* tile) {
+    const int nmax = std::max(f->n[0], std::max(f->n[1], f->n[2]));
+    const int tmin = (nmax + 255) / 256;  // at most 2^24 buckets
+    if (c.variant == 0 && c.sort_tile > 0) {
+        const int first = c.sort_tile <= 6 ? 4 : 8;
+        for (int T : {first, 12 - first}) {
+            if (T >= tmin && batch_tile_supported(f->desc.coef, f->N, f->C, T)) {
+                *mode = T == 4 ? MODE_TILE4 : MODE_TILE8;
+                *tile = T;
+                return;
+            }
+        }
+    }
+    *mode = MODE_DIRECT;
+    *tile = std::max(c.sort_tile > 0 ? c.sort_tile : 8, tmin);
+}
+
+size_t bin_bucket_count(const bsi_field* f, int tile);  // eval.hip
+
+static bsi_status enqueue(bsi_batch* b, hipStream_t s) {
+    bsi_ctx* ctx = b->ctx;
+    if (b->nitems == 0) return BSI_OK;
+    const BatchArgs& a = b->args;
+    const unsigned fillb = unsigned(std::min<uint64_t>((b->Btot + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_fill_u32, dim3(fillb), dim3(256), 0, s, a.hist, long(b->Btot), 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, a.ctr, 2L, 0u);
+    {
+        StageTimer tm(ctx, "batch_bin", s);
+        hipLaunchKernelGGL(k_batch_bin_count, dim3(b->npblocks), dim3(BLK), 0, s, a);
+        hipLaunchKernelGGL(k_scan_sums, dim3(unsigned(b->nsums)), dim3(SCAN_BLOCK), 0, s, a.hist, long(b->Btot),
+                           a.offs + b->Btot);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, a.offs + b->Btot, int(b->nsums));
+        hipLaunchKernelGGL(k_scan_apply, dim3(unsigned(b->nsums)), dim3(SCAN_BLOCK), 0, s, a.hist, long(b->Btot),
+                           a.offs + b->Btot, a.offs);
+        hipLaunchKernelGGL(k_batch_bin_scatter, dim3(b->npblocks), dim3(BLK), 0, s, a);
+        if (b->nbblocks) hipLaunchKernelGGL(k_batch_compact, dim3(b->nbblocks), dim3(BLK), 0, s, a);
+    }
+    {
+        StageTimer tm(ctx, "batch_gather", s);
+        launch_gather(b->coef, b->grad, b->grid, b->lds, s, a);
+    }
+    BSI_HIP(hipGetLastError());
+    return BSI_OK;
+}
+
+}  // namespace bsi
+
+extern "C" {
+
+bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t count,
+                            const bsi_eval_config* cfgs, bsi_batch** out) {
+    clear_error();
+    BSI_CHECK(ctx && out, BSI_E_INVAL, "NULL argument");
+    *out = nullptr;
+    BSI_CHECK(count >= 1 && count <= 65535, BSI_E_INVAL, "count must be in [1, 65535]");
+    BSI_CHECK(items != nullptr, BSI_E_INVAL, "items is NULL");
+    const bsi_field* f0 = items[0].field;
+    BSI_CHECK(f0 != nullptr, BSI_E_INVAL, "item 0 has no field");
+    const int coef = f0->desc.coef;
+    // grad presence is judged on the items with particles (empty tensors may
+    // come with NULL pointers)
+    bool grad = items[0].grad != nullptr;
+    for (int i = 0; i < count; ++i)
+        if (items[i].P > 0) {
+            grad = items[i].grad != nullptr;
+            break;
+        }
+    uint64_t Ptot = 0;
+    for (int i = 0; i < count; ++i) {
+        const bsi_eval_item& it = items[i];
+        const std::string tag = "item " + std::to_string(i) + ": ";
+        BSI_CHECK(it.field != nullptr, BSI_E_INVAL, tag + "field is NULL");
+        BSI_CHECK(it.field->ctx == ctx, BSI_E_INVAL, tag + "field belongs to another context");
+        BSI_CHECK(it.field->desc.coef == coef, BSI_E_INVAL,
+                  tag + "a batch holds fields of one coefficient type");
+        BSI_CHECK(it.P >= 0 && it.P < (int64_t(1) << 31), BSI_E_INVAL, tag + "P must be in [0, 2^31)");
+        if (it.P == 0) continue;
+        BSI_CHECK((it.grad != nullptr) == grad, BSI_E_INVAL,
+                  tag + "grad must be given for every item of a batch or for none");
+        BSI_TRY(check_device_ptr_ex(it.pos, (tag + "pos").c_str()));
+        BSI_TRY(check_device_ptr_ex(it.u, (tag + "u").c_str()));
+        if (grad) BSI_TRY(check_device_ptr_ex(it.grad, (tag + "grad").c_str()));
+        if (cfgs) {
+            const bsi_eval_config& c = cfgs[i];
+            BSI_CHECK(c.sort_tile >= 0 && c.sort_tile <= 1024, BSI_E_INVAL, tag + "sort_tile out of range");
+        }
+        Ptot += uint64_t(it.P);
+    }
+    BSI_CHECK(Ptot < (uint64_t(1) << 31), BSI_E_INVAL, "a batch holds fewer than 2^31 particles");
+    BSI_HIP(hipSetDevice(ctx->device));
+
+    auto* b = new (std::nothrow) bsi_batch();
+    BSI_CHECK(b != nullptr, BSI_E_NOMEM, "host allocation failed");
+    b->ctx = ctx;
+    b->coef = coef;
+    b->grad = grad;
+    b->cfgs.resize(count);
+    std::vector<BatchItem> hi;
+    std::vector<uint16_t> pblock, bblock, dunit;
+    uint64_t Btot = 0, pbase = 0;
+    int lds = 0;
+    for (int i = 0; i < count; ++i) {
+        const bsi_eval_item& it = items[i];
+        bsi_field* f = it.field;
+        bsi_eval_config c{};
+        if (cfgs) c = cfgs[i];
+        else if (bsi_status st = lookup_config(ctx, f, it.P, &c); st != BSI_OK) {
+            delete b;
+            return st;
+        }
+        b->cfgs[i] = c;
+        if (it.P == 0) continue;
+        int mode = 0, tile = 0;
+        item_mode(f, c, &mode, &tile);
+        b->cfgs[i].variant = mode == MODE_DIRECT ? 1 : 0;
+        b->cfgs[i].sort_tile = tile;
+        BatchItem x{};
+        GatherArgs& g = x.ga;
+        g.grid = f->grid;
+        g.pos = it.pos;
+        g.u = it.u;
+        g.grad = it.grad;
+        g.nonfinite = f->counters;
+        g.P = long(it.P);
+        g.n0 = f->n[0];
+        g.n1 = f->n[1];
+        g.n2 = f->n[2];
+        g.P1 = f->P[1];
+        g.P2 = f->P[2];
+        g.pitch2 = f->pitch2;
+        g.ih0 = f->inv_h[0];
+        g.ih1 = f->inv_h[1];
+        g.ih2 = f->inv_h[2];
+        g.xcd_remap = 0;
+        g.tiles_per_group = 1;
+        const size_t nbf = bin_bucket_count(f, tile);
+        g.nbuckets_finite = uint32_t(nbf);
+        x.N = f->N;
+        x.C = f->C;
+        x.mode = mode;
+        x.tile = tile;
+        x.pbase = uint32_t(pbase);
+        x.bbase = uint32_t(Btot);
+        x.nb = uint32_t(nbf + 1);
+        x.pblk = uint32_t(pblock.size());
+        const uint16_t id = uint16_t(hi.size());
+        pblock.insert(pblock.end(), size_t((it.P + BLK - 1) / BLK), id);
+        if (mode == MODE_DIRECT) {
+            x.ubase = uint32_t(dunit.size());
+            dunit.insert(dunit.end(), size_t((it.P + BATCH_B - 1) / BATCH_B), id);
+        } else {
+            x.bblk = uint32_t(bblock.size());
+            bblock.insert(bblock.end(), size_t((x.nb + BLK - 1) / BLK), id);
+            lds = std::max(lds, batch_tile_lds(coef, f->N, f->C, tile));
+        }
+        hi.push_back(x);
+        pbase += uint64_t(it.P);
+        Btot += nbf + 1;
+    }
+    if (Btot >= (uint64_t(1) << 32)) {
+        delete b;
+        set_error("too many buckets in one batch; use coarser sort tiles");
+        return BSI_E_INVAL;
+    }
+    b->nitems = int(hi.size());
+    b->Ptot = pbase;
+    b->Btot = Btot;
+    b->npblocks = uint32_t(pblock.size());
+    b->nbblocks = uint32_t(bblock.size());
+    b->ndirect = uint32_t(dunit.size());
+    b->nsums = (Btot + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    b->lds = size_t(lds);
+    if (b->nitems == 0) {
+        *out = b;
+        return BSI_OK;
+    }
+    // workspace: tables, histogram + offsets (+ scan sums), keys, ranks, perm,
+    // binned positions, tile list, counters
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t o_items = take(hi.size() * sizeof(BatchItem));
+    const size_t o_pblock = take(pblock.size() * sizeof(uint16_t));
+    const size_t o_bblock = take(std::max<size_t>(bblock.size(), 1) * sizeof(uint16_t));
+    const size_t o_dunit = take(std::max<size_t>(dunit.size(), 1) * sizeof(uint16_t));
+    const size_t o_hist = take(Btot * sizeof(uint32_t));
+    const size_t o_offs = take((Btot + b->nsums) * sizeof(uint32_t));
+    const size_t o_key = take(pbase * sizeof(uint32_t));
+    const size_t o_rank = take(pbase * sizeof(uint32_t));
+    const size_t o_perm = take(pbase * sizeof(uint32_t));
+    const size_t o_pos = take(3 * pbase * sizeof(double));
+    const size_t o_list = take(std::max<uint64_t>(Btot, 1) * sizeof(uint2));
+    const size_t o_ctr = take(2 * sizeof(uint32_t));
+    b->ws_bytes = off;
+    if (hipMalloc(&b->ws, off) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        set_error("batch workspace allocation of " + std::to_string(off) + " bytes failed");
+        return BSI_E_NOMEM;
+    }
+    char* base = static_cast<char*>(b->ws);
+    BatchArgs& a = b->args;
+    a.items = reinterpret_cast<const BatchItem*>(base + o_items);
+    a.pblock_item = reinterpret_cast<const uint16_t*>(base + o_pblock);
+    a.bblock_item = reinterpret_cast<const uint16_t*>(base + o_bblock);
+    a.dunit_item = reinterpret_cast<const uint16_t*>(base + o_dunit);
+    a.hist = reinterpret_cast<uint32_t*>(base + o_hist);
+    a.offs = reinterpret_cast<uint32_t*>(base + o_offs);
+    a.key = reinterpret_cast<uint32_t*>(base + o_key);
+    a.rank = reinterpret_cast<uint32_t*>(base + o_rank);
+    a.perm = reinterpret_cast<uint32_t*>(base + o_perm);
+    a.pos_sorted = reinterpret_cast<double*>(base + o_pos);
+    a.tile_list = reinterpret_cast<uint2*>(base + o_list);
+    a.ctr = reinterpret_cast<uint32_t*>(base + o_ctr);
+    a.ndirect = b->ndirect;
+    for (auto& x : hi) {
+        x.ga.hist = a.hist + x.bbase;
+        x.ga.offs = a.offs + x.bbase;
+        x.ga.perm = a.perm;
+        x.ga.pos_sorted = a.pos_sorted;
+    }
+    bsi_status st = BSI_OK;
+    auto up = [&](size_t o, const void* src, size_t bytes) {
+        if (st == BSI_OK && bytes && hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("upload of the batch tables failed");
+            st = BSI_E_DEVICE;
+        }
+    };
+    up(o_items, hi.data(), hi.size() * sizeof(BatchItem));
+    up(o_pblock, pblock.data(), pblock.size() * sizeof(uint16_t));
+    up(o_bblock, bblock.data(), bblock.size() * sizeof(uint16_t));
+    up(o_dunit, dunit.data(), dunit.size() * sizeof(uint16_t));
+    // persistent grid: as many one-wavefront workgroups as stay resident
+    int per_cu = 0;
+    if (st == BSI_OK && hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &per_cu, gather_kernel(coef, grad), BATCH_B, b->lds) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = 0;
+    }
+    per_cu = std::max(1, std::min(per_cu, 32));
+    b->grid = unsigned(per_cu * ctx->num_cus);
+    if (st != BSI_OK) {
+        (void)hipFree(b->ws);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return BSI_OK;
+}
+
+bsi_status bsi_batch_run(bsi_batch* b, int32_t use_graph, void* stream) {
+    clear_error();
+    BSI_CHECK(b != nullptr, BSI_E_INVAL, "batch is NULL");
+    BSI_HIP(hipSetDevice(b->ctx->device));
+    hipStream_t s = pick_stream(b->ctx, stream);
+    if (!use_graph) return enqueue(b, s);
+    if (!b->exec) {
+        // capture once on a private stream; the graph is then launched on `s`
+        if (!b->cap_stream) BSI_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        BSI_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        const bsi_status st = enqueue(b, b->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+        if (st != BSI_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        BSI_CHECK(e == hipSuccess && g, BSI_E_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+        b->graph = g;
+        BSI_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    StageTimer tm(b->ctx, "batch_graph", s);
+    BSI_HIP(hipGraphLaunch(b->exec, s));
+    return BSI_OK;
+}
+
+bsi_status bsi_batch_item_config(const bsi_batch* b, int32_t item, bsi_eval_config* cfg) {
+    clear_error();
+    BSI_CHECK(b && cfg, BSI_E_INVAL, "NULL argument");
+    BSI_CHECK(item >= 0 && item < int32_t(b->cfgs.size()), BSI_E_INVAL, "item out of range");
+    *cfg = b->cfgs[item];
+    return BSI_OK;
+}
+
+size_t bsi_batch_bytes(const bsi_batch* b) { return b ? b->ws_bytes : 0; }
+
+void bsi_batch_destroy(bsi_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->ws) (void)hipFree(b->ws);
+    delete b;
+}
+
+bsi_status bsi_eval_batch(bsi_ctx* ctx, const bsi_eval_item* items, int32_t count, void* stream) {
+    bsi_batch* b = nullptr;
+    BSI_TRY(bsi_batch_create(ctx, items, count, nullptr, &b));
+    hipStream_t s = pick_stream(ctx, stream);
+    bsi_status st = bsi_batch_run(b, 0, s);
+    if (st == BSI_OK && hipStreamSynchronize(s) != hipSuccess) {
+        set_error(std::string("batch failed: ") + hipGetErrorString(hipGetLastError()));
+        st = BSI_E_DEVICE;
+    }
+    bsi_batch_destroy(b);
+    return st;
+}
+
+}  // extern "C"

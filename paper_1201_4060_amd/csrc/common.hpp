@@ -142,7 +142,8 @@ struct bsi_ctx {
     // per-stream scratch, grown on demand
     std::map<hipStream_t, bsi::Workspace> fft_ws;
     std::map<hipStream_t, bsi::Workspace> eval_ws;
-    bsi_eval_config tuned{};  // defaults for bsi_eval
+    // tuned evaluation configurations keyed by (order, coef, ncomp, density class)
+    std::map<std::tuple<int, int, int, int>, bsi_eval_config> tune_table;
     int live_fields = 0;
     // stage timing (hipEvent pairs recorded around kernel launches)
     bool timing = false;
@@ -203,6 +204,8 @@ bsi_status grid_from_dense(bsi_field* f, const double* dense, hipStream_t s);
 bsi_status grid_to_dense(const bsi_field* f, double* dense, hipStream_t s);
 bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
                     const bsi_eval_config& cfg, hipStream_t s);
+bsi_status lookup_config(bsi_ctx* ctx, const bsi_field* f, int64_t P, bsi_eval_config* out);
+bsi_status check_device_ptr_ex(const void* p, const char* what);
 bsi_status debug_cells_run(bsi_field* f, const double* pos, int64_t P, int32_t* cell, double* t,
                            hipStream_t s);
 

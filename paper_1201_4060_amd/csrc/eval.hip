@@ -1,45 +1,10 @@
 // Evaluation on the GPU: position -> cell/offset, Morton binning, and the
 // per-particle gather + tensor contraction (Sections 2, 3, 5; Table 1).
 #include <algorithm>
-#include <utility>
 
-#include "common.hpp"
+#include "gather.hpp"
 
 namespace bsi {
-
-// ---------------------------------------------------------- cell / offset ---
-// Section 5 stencil rule in grid units: s = x * (n/L) as one FP64 product,
-// f = floor(s), t = s - f, cell = f mod n (exact Euclidean remainder).
-// Contraction is off so that s - f is not fused into an FMA with x * inv_h.
-// Returns false when s is not finite.
-__device__ __forceinline__ bool cell_of(double x, double inv_h, int n, int& cell, double& t) {
-#pragma clang fp contract(off)
-    const double s = x * inv_h;
-    if (!isfinite(s)) return false;
-    const double f = floor(s);
-    t = s - f;
-    if (f >= 0.0 && f < double(n)) {     // the usual case: x already in [0, L)
-        cell = int(f);
-        return true;
-    }
-    if (fabs(f) < 9007199254740992.0) {  // |f| < 2^53: exact in int64
-        long long m = static_cast<long long>(f) % n;
-        if (m < 0) m += n;
-        cell = int(m);
-    } else {                             // f = integer-valued double, fmod is exact
-        double r = fmod(f, double(n));
-        if (r < 0) r += double(n);
-        cell = int(r);
-    }
-    return true;
-}
-
-struct CellArgs {
-    const double* pos;
-    long P;
-    int n0, n1, n2;
-    double ih0, ih1, ih2;
-};
 
 __global__ void k_debug_cells(CellArgs a, int32_t* cell, double* t) {
     const long p = blockIdx.x * long(blockDim.x) + threadIdx.x;
@@ -59,17 +24,6 @@ __global__ void k_debug_cells(CellArgs a, int32_t* cell, double* t) {
 }
 
 // ---------------------------------------------------------------- binning ---
-// Particles are counting-sorted by the Morton code of the tile (cell / T) that
-// holds their cell; non-finite particles go to one extra bucket at the end.
-
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 bits -> every third bit
-    v &= 0x3ffu;
-    v = (v | (v << 16)) & 0x030000ffu;
-    v = (v | (v << 8)) & 0x0300f00fu;
-    v = (v | (v << 4)) & 0x030c30c3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
 
 __global__ void k_bin_count(CellArgs a, int tile, uint32_t nbuckets_finite, uint32_t* __restrict__ hist,
                             uint32_t* __restrict__ key, uint32_t* __restrict__ rank) {
@@ -90,81 +44,6 @@ __global__ void k_bin_count(CellArgs a, int tile, uint32_t nbuckets_finite, uint
     rank[p] = atomicAdd(&hist[k], 1u);
 }
 
-// Exclusive scan of hist[0..n) in three steps: per-block sums, a single-block
-// scan of those sums, per-block scan plus offset.
-constexpr int SCAN_BLOCK = 256;
-constexpr int SCAN_ITEMS = 4;
-constexpr int SCAN_CHUNK = SCAN_BLOCK * SCAN_ITEMS;
-
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
-    // Hillis-Steele in LDS over SCAN_BLOCK threads
-    const int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
-        const uint32_t add = tid >= off ? sh[tid - off] : 0u;
-        __syncthreads();
-        sh[tid] += add;
-        __syncthreads();
-    }
-    const uint32_t incl = sh[tid];
-    *total = sh[SCAN_BLOCK - 1];
-    __syncthreads();
-    return incl - v;
-}
-
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(const uint32_t* __restrict__ in, long n,
-                                                          uint32_t* __restrict__ sums) {
-    __shared__ uint32_t sh[SCAN_BLOCK];
-    const long base = long(blockIdx.x) * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
-    uint32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i)
-        if (base + i < n) s += in[base + i];
-    uint32_t total;
-    block_exclusive_scan(s, sh, &total);
-    if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-// single block: exclusive scan of sums[0..m) in place (m <= SCAN_BLOCK * items)
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(uint32_t* sums, int m) {
-    __shared__ uint32_t sh[SCAN_BLOCK];
-    const int per = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    const int beg = threadIdx.x * per;
-    uint32_t s = 0;
-    for (int i = 0; i < per; ++i)
-        if (beg + i < m) s += sums[beg + i];
-    uint32_t total;
-    uint32_t run = block_exclusive_scan(s, sh, &total);
-    for (int i = 0; i < per; ++i)
-        if (beg + i < m) {
-            const uint32_t v = sums[beg + i];
-            sums[beg + i] = run;
-            run += v;
-        }
-}
-
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const uint32_t* __restrict__ in, long n,
-                                                           const uint32_t* __restrict__ sums,
-                                                           uint32_t* __restrict__ out) {
-    __shared__ uint32_t sh[SCAN_BLOCK];
-    const long base = long(blockIdx.x) * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
-    uint32_t v[SCAN_ITEMS];
-    uint32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        v[i] = (base + i < n) ? in[base + i] : 0u;
-        s += v[i];
-    }
-    uint32_t total;
-    uint32_t run = block_exclusive_scan(s, sh, &total) + sums[blockIdx.x];
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        if (base + i < n) out[base + i] = run;
-        run += v[i];
-    }
-}
-
 // perm[dst] = p and, when pos_sorted is given, a copy of the particle's
 // position at its binned slot (so that the gather reads binned positions
 // contiguously instead of through perm).
@@ -183,460 +62,26 @@ __global__ void k_bin_scatter(long P, const uint32_t* __restrict__ key, const ui
     }
 }
 
-__global__ void k_fill_u32(uint32_t* p, long n, uint32_t v) {
-    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x)
-        p[i] = v;
-}
-
 // ----------------------------------------------------------------- gather ---
 
-template <typename CT>
-struct Acc {
-    using type = float;
-};
-template <>
-struct Acc<double> {
-    using type = double;
-};
-
-template <typename CT, typename AT>
-__device__ __forceinline__ AT widen(CT v) {
-    if constexpr (sizeof(CT) == 2) return AT(__uint_as_float(uint32_t(v) << 16));
-    else return AT(v);
-}
-
-// w_j(t) = sum_i M[j][i] t^i and w'_j(t) = sum_i M1[j][i] t^i (Horner), M from
-// the Section 7 general formula at compile time.
-template <int N, typename AT>
-__device__ __forceinline__ void bspline_weights(AT t, AT* w, AT* wd) {
-    constexpr BSpline<N> B{};
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        AT acc = AT(B.M[j][N - 1]);
-#pragma unroll
-        for (int i = N - 2; i >= 0; --i) acc = acc * t + AT(B.M[j][i]);
-        w[j] = acc;
-        AT dacc = AT(B.M1[j][N - 2]);
-#pragma unroll
-        for (int i = N - 3; i >= 0; --i) dacc = dacc * t + AT(B.M1[j][i]);
-        wd[j] = dacc;
-    }
-}
-
-struct GatherArgs {
-    const void* grid;
-    const double* pos;
-    const uint32_t* perm;    // binned order, or nullptr
-    const double* pos_sorted;  // positions in binned order (tiled kernel), or nullptr
-    const uint32_t* hist;    // particles per bucket (tiled kernel)
-    const uint32_t* offs;    // first binned index per bucket (tiled kernel)
-    void* u;
-    void* grad;
-    unsigned long long* nonfinite;
-    long P;
-    int n0, n1, n2;
-    int P1, P2;  // padded extents of axes 1 and 2
-    int pitch2;  // elements between consecutive (p0, p1) rows of the grid
-    double ih0, ih1, ih2;
-    int xcd_remap;
-    uint32_t nbuckets_finite;
-    uint32_t tiles_per_group;
-};
-
-__device__ __forceinline__ long logical_block(int remap) {
-    const long b = blockIdx.x;
-    if (!remap) return b;
-    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD one
-    // contiguous range of logical blocks (a compact region of binned particles).
-    const long B = gridDim.x;
-    const long q = B / 8, r = B % 8;
-    const long x = b % 8, i = b / 8;
-    return x * q + (x < r ? x : r) + i;
-}
-
-template <typename AT, int C, bool GRAD>
-__device__ __forceinline__ void write_nan(const GatherArgs& a, long p) {
-    const AT nan = AT(__builtin_nan(""));
-    AT* u = static_cast<AT*>(a.u) + p * C;
-#pragma unroll
-    for (int c = 0; c < C; ++c) u[c] = nan;
-    if constexpr (GRAD) {
-        AT* g = static_cast<AT*>(a.grad) + p * C * 3;
-#pragma unroll
-        for (int c = 0; c < 3 * C; ++c) g[c] = nan;
-    }
-}
-
-// Cell and weights of particle p (Section 5 stencil, Section 2 weights).
-template <int N, typename AT>
-__device__ __forceinline__ bool particle_setup_x(const GatherArgs& a, const double* x, int* cell,
-                                                 AT (*w)[N], AT (*wd)[N]) {
-    const int n[3] = {a.n0, a.n1, a.n2};
-    const double ih[3] = {a.ih0, a.ih1, a.ih2};
-    double t[3];
-    bool ok = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) ok = cell_of(x[d], ih[d], n[d], cell[d], t[d]) && ok;
-    if (!ok) return false;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        bspline_weights<N, AT>(AT(t[d]), w[d], wd[d]);
-        const AT s = AT(ih[d]);
-#pragma unroll
-        for (int k = 0; k < N; ++k) wd[d][k] *= s;
-    }
-    return true;
-}
-
-template <int N, typename AT>
-__device__ __forceinline__ bool particle_setup(const GatherArgs& a, long p, int* cell, AT (*w)[N],
-                                               AT (*wd)[N]) {
-    const double x[3] = {a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]};
-    return particle_setup_x<N, AT>(a, x, cell, w, wd);
-}
-
-// Tensor contraction of the N^3 (x C) local coefficients with the weights.
-// Order follows the Table 1 idea (reduce the tensor order as early as
-// possible): each contiguous row of N points along axis 2 is reduced with w2
-// and w2' first, then axis 1 with w1 / w1', then axis 0.  The axis-0 sum is
-// split into two fixed halves (ia < N/2 and ia >= N/2) that are added at the
-// end, so that one particle can also be shared by two lanes; every gather
-// variant uses exactly this arithmetic, so their results are bitwise equal.
-// `row(ia, ib)` returns a pointer to the N*C coefficients of row (ia, ib).
-template <typename AT, int C>
-struct Partial {
-    AT u[C], g0[C], g1[C], g2[C];
-};
-
-// One axis-0 plane: rows row(ib), ib < N, reduced along axis 2 then axis 1,
-// accumulated into out with the plane's axis-0 weights w0k, wd0k.
-template <int N, typename CT, typename AT, int C, bool GRAD, bool FENCE, typename PlaneRowFn>
-__device__ __forceinline__ void contract_plane(AT w0k, AT wd0k, const AT (*w)[N], const AT (*wd)[N],
-                                               PlaneRowFn row, Partial<AT, C>& out) {
-    AT v[C], v1[C], v2[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) v[c] = v1[c] = v2[c] = AT(0);
-#pragma unroll
-    for (int ib = 0; ib < N; ++ib) {
-        const auto* r = row(ib);
-        CT raw[N * C];
-#pragma unroll
-        for (int e = 0; e < N * C; ++e) raw[e] = r[e];
-        AT tr[C], trd[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) tr[c] = trd[c] = AT(0);
-#pragma unroll
-        for (int e = 0; e < N; ++e) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const AT val = widen<CT, AT>(raw[e * C + c]);
-                tr[c] += w[2][e] * val;
-                if constexpr (GRAD) trd[c] += wd[2][e] * val;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            v[c] += w[1][ib] * tr[c];
-            if constexpr (GRAD) {
-                v1[c] += wd[1][ib] * tr[c];
-                v2[c] += w[1][ib] * trd[c];
-            }
-        }
-        if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        out.u[c] += w0k * v[c];
-        if constexpr (GRAD) {
-            out.g0[c] += wd0k * v[c];
-            out.g1[c] += w0k * v1[c];
-            out.g2[c] += w0k * v2[c];
-        }
-    }
-}
-
-// NIA consecutive axis-0 planes: w0[k], wd0[k] are the axis-0 weights of
-// plane k and row(k, ib) its rows; accumulation order is k = 0..NIA-1.
-// FENCE (LDS-resident rows): planes run as a loop so that only one plane's
-// rows are live at a time; otherwise everything is unrolled.
-template <int N, typename CT, typename AT, int C, bool GRAD, int NIA, bool FENCE = false, typename RowFn>
-__device__ __forceinline__ void contract_planes(const AT* w0, const AT* wd0, const AT (*w)[N],
-                                                const AT (*wd)[N], RowFn row, Partial<AT, C>& out) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) out.u[c] = out.g0[c] = out.g1[c] = out.g2[c] = AT(0);
-    if constexpr (FENCE) {
-#pragma unroll 1
-        for (int k = 0; k < NIA; ++k) {
-            AT w0k = w0[0], wd0k = wd0[0];
-#pragma unroll
-            for (int q = 1; q < NIA; ++q) {
-                w0k = (k == q) ? w0[q] : w0k;
-                wd0k = (k == q) ? wd0[q] : wd0k;
-            }
-            contract_plane<N, CT, AT, C, GRAD, true>(w0k, wd0k, w, wd, [&](int ib) { return row(k, ib); },
-                                                    out);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < NIA; ++k)
-            contract_plane<N, CT, AT, C, GRAD, false>(w0[k], wd0[k], w, wd,
-                                                     [&](int ib) { return row(k, ib); }, out);
-    }
-}
-
-template <typename AT, int C, bool GRAD>
-__device__ __forceinline__ void store_sum(const GatherArgs& a, long p, const Partial<AT, C>& lo,
-                                          const Partial<AT, C>& hi) {
-    AT* u = static_cast<AT*>(a.u) + p * C;
-#pragma unroll
-    for (int c = 0; c < C; ++c) u[c] = lo.u[c] + hi.u[c];
-    if constexpr (GRAD) {
-        AT* g = static_cast<AT*>(a.grad) + p * C * 3;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            g[3 * c + 0] = lo.g0[c] + hi.g0[c];
-            g[3 * c + 1] = lo.g1[c] + hi.g1[c];
-            g[3 * c + 2] = lo.g2[c] + hi.g2[c];
-        }
-    }
-}
-
-template <int N, typename CT, typename AT, int C, bool GRAD, bool FENCE = false, typename RowFn>
-__device__ __forceinline__ void contract_and_store(const GatherArgs& a, long p, const AT (*w)[N],
-                                                   const AT (*wd)[N], RowFn row) {
-    Partial<AT, C> lo, hi;
-    contract_planes<N, CT, AT, C, GRAD, N / 2, FENCE>(w[0], wd[0], w, wd, row, lo);
-    contract_planes<N, CT, AT, C, GRAD, N / 2, FENCE>(
-        w[0] + N / 2, wd[0] + N / 2, w, wd, [&](int k, int ib) { return row(N / 2 + k, ib); }, hi);
-    store_sum<AT, C, GRAD>(a, p, lo, hi);
-}
-
-// Direct variant: one thread per particle, stencil rows read from global
-// memory (caches provide the reuse between neighbouring binned particles).
+// Direct variant: one thread per particle.
 template <int N, typename CT, int C, bool GRAD>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
-    using AT = typename Acc<CT>::type;
     const long j = logical_block(a.xcd_remap) * blockDim.x + threadIdx.x;
     if (j >= a.P) return;
-    const long p = a.perm ? long(a.perm[j]) : j;
-    int cell[3];
-    AT w[3][N], wd[3][N];
-    if (!particle_setup<N, AT>(a, p, cell, w, wd)) {
-        write_nan<AT, C, GRAD>(a, p);
-        atomicAdd(a.nonfinite, 1ull);
-        return;
-    }
-    const CT* base = static_cast<const CT*>(a.grid) + (long(cell[0]) * a.P1 + cell[1]) * a.pitch2 +
-                     long(cell[2]) * C;
-    const long rowA = long(a.P1) * a.pitch2;
-    const long rowB = a.pitch2;
-    contract_and_store<N, CT, AT, C, GRAD>(a, p, w, wd,
-                                           [&](int ia, int ib) { return base + ia * rowA + ib * rowB; });
+    direct_eval<N, CT, C, GRAD>(a, j);
 }
 
-__device__ __forceinline__ uint32_t compact3(uint32_t v) {  // inverse of spread3
-    v &= 0x09249249u;
-    v = (v | (v >> 2)) & 0x030c30c3u;
-    v = (v | (v >> 4)) & 0x0300f00fu;
-    v = (v | (v >> 8)) & 0x030000ffu;
-    v = (v | (v >> 16)) & 0x000003ffu;
-    return v;
-}
-
-// Geometry of one LDS tile: the (T+N-1)^3 block of the ghost-padded grid that
-// holds the stencils of a T^3 tile of cells, each row of (T+N-1)*C elements
-// rounded up to whole 16-byte chunks.
-template <int N, typename CT, int C, int T>
-struct TileGeom {
-    static constexpr int R = T + N - 1;
-    static constexpr int VEC = 16 / int(sizeof(CT));   // elements per 16-byte chunk
-    static constexpr int CH = (R * C + VEC - 1) / VEC;  // chunks per row
-    static constexpr int LROW = CH * VEC;               // LDS row pitch (elements)
-    static constexpr int ROWS = R * R;
-    static constexpr int SLOTS = ROWS * CH;
-    static constexpr int PER = (SLOTS + 63) / 64;       // chunks per lane
-    static constexpr int BYTES = SLOTS * 16;
-    // tile origins must start on 16-byte boundaries inside a row
-    static constexpr bool ALIGNED = (T * C * int(sizeof(CT))) % 16 == 0;
-};
-
-template <typename AT>
-__device__ __forceinline__ AT shfl_xor1(AT v) {
-    return __shfl_xor(v, 1, 64);
-}
-
-// Barrier for LDS only: orders the wavefront's LDS accesses without waiting for
-// outstanding global loads (the next tile's prefetch stays in flight).
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-__device__ __forceinline__ uint32_t next_tile(const GatherArgs& a, uint32_t b, uint32_t end) {
-    while (b < end && a.hist[b] == 0) ++b;
-    return b;
-}
-
-// Issue the 16-byte loads of the LDS block of tile `bucket` into registers.
-// Rows outside the padded grid (partial tiles only; never read by a particle)
-// load the tile origin instead; chunks past a row's end read the next row or
-// the allocation's slack.  The slots are expanded at compile time (no loop)
-// so that the register array is indexed by constants only.
-template <int N, typename CT, int C, int T>
-struct TileLoad {
-    using G = TileGeom<N, CT, C, T>;
-    const uint4* g;
-    int p0v, p1v, lim0, lim1, lane;
-
-    __device__ __forceinline__ TileLoad(const GatherArgs& a, uint32_t bucket, int lane_) : lane(lane_) {
-        const int o0 = int(compact3(bucket >> 2)) * T;
-        const int o1 = int(compact3(bucket >> 1)) * T;
-        const int o2 = int(compact3(bucket)) * T;
-        lim0 = a.n0 + N - 1 - o0;
-        lim1 = a.n1 + N - 1 - o1;
-        g = reinterpret_cast<const uint4*>(static_cast<const CT*>(a.grid) +
-                                           (long(o0) * a.P1 + o1) * long(a.pitch2) + long(o2) * C);
-        p1v = a.pitch2 / G::VEC;  // row pitch in chunks (offsets inside a tile stay < 2^31)
-        p0v = a.P1 * p1v;
-    }
-    template <int Q>
-    __device__ __forceinline__ uint4 slot() const {
-        const int sl = Q * 64 + lane;
-        const int row = sl / G::CH;
-        const int ch = sl - row * G::CH;
-        const int r0 = row / G::R;
-        const int r1 = row - r0 * G::R;
-        const bool ok = sl < G::SLOTS && r0 < lim0 && r1 < lim1;
-        return g[ok ? r0 * p0v + r1 * p1v + ch : 0];
-    }
-    template <size_t... Q>
-    __device__ __forceinline__ void issue(uint4 (&pre)[G::PER], std::index_sequence<Q...>) const {
-        ((pre[Q] = slot<int(Q)>()), ...);
-    }
-};
-
-template <int N, typename CT, int C, int T>
-__device__ __forceinline__ void tile_issue(const GatherArgs& a, uint32_t bucket,
-                                           uint4 (&pre)[TileGeom<N, CT, C, T>::PER], int lane) {
-    TileLoad<N, CT, C, T> tl(a, bucket, lane);
-    tl.issue(pre, std::make_index_sequence<TileGeom<N, CT, C, T>::PER>{});
-}
-
-template <int N, typename CT, int C, int T, size_t... Q>
-__device__ __forceinline__ void tile_store_impl(uint4* lds, const uint4 (&pre)[TileGeom<N, CT, C, T>::PER],
-                                                int lane, std::index_sequence<Q...>) {
-    using G = TileGeom<N, CT, C, T>;
-    (((int(Q) * 64 + 64 <= G::SLOTS || int(Q) * 64 + lane < G::SLOTS) ? (void)(lds[Q * 64 + lane] = pre[Q])
-                                                                      : (void)0),
-     ...);
-}
-
-template <int N, typename CT, int C, int T>
-__device__ __forceinline__ void tile_store(uint4* lds, const uint4 (&pre)[TileGeom<N, CT, C, T>::PER],
-                                           int lane) {
-    tile_store_impl<N, CT, C, T>(lds, pre, lane, std::make_index_sequence<TileGeom<N, CT, C, T>::PER>{});
-}
-
-// LDS-tiled variant.  One workgroup of B threads walks `tiles_per_group`
-// consecutive Morton tiles (T^3 cells each).  For each tile, all 16-byte loads
-// of its LDS block are issued at once (one memory round trip) together with
-// the tile's binned positions (contiguous); the block is stored to LDS and the
-// particles are evaluated from it: two lanes per particle (one half of the
-// axis-0 sum each, combined with a lane shuffle) while the tile holds at most
-// B/2 particles, one lane per particle otherwise.
+// LDS-tiled variant: one workgroup of B threads walks `tiles_per_group`
+// consecutive Morton tiles (T^3 cells each), skipping empty ones.
 template <int N, typename CT, int C, bool GRAD, int T, int B>
 __global__ __launch_bounds__(B) void k_gather_tiled(GatherArgs a) {
-    using AT = typename Acc<CT>::type;
-    using G = TileGeom<N, CT, C, T>;
-    constexpr int PERB = (G::SLOTS + B - 1) / B;
-    __shared__ uint4 tile_v[PERB * B];
-    const CT* tile = reinterpret_cast<const CT*>(tile_v);
-    const int tid = threadIdx.x;
+    __shared__ u32x4 tile_v[tile_lds_bytes<N, CT, C, T, B>() / 16];
     const uint32_t nbt = a.nbuckets_finite + 1;
     const uint32_t b0 = uint32_t(logical_block(a.xcd_remap)) * a.tiles_per_group;
     const uint32_t b1 = min(b0 + a.tiles_per_group, nbt);
-    for (uint32_t cur = next_tile(a, b0, b1); cur < b1; cur = next_tile(a, cur + 1, b1)) {
-        const uint32_t count = a.hist[cur];
-        const uint32_t start = a.offs[cur];
-        if (cur == a.nbuckets_finite) {  // particles without a cell (the last bucket)
-            for (uint32_t j = tid; j < count; j += B) write_nan<AT, C, GRAD>(a, long(a.perm[start + j]));
-            if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
-            break;
-        }
-        const int o0 = int(compact3(cur >> 2)) * T;
-        const int o1 = int(compact3(cur >> 1)) * T;
-        const int o2 = int(compact3(cur)) * T;
-        const bool pair = count <= uint32_t(B / 2);
-        const int stride = pair ? B / 2 : B;
-        const uint32_t jlane = pair ? uint32_t(tid >> 1) : uint32_t(tid);
-        const int half = pair ? (tid & 1) : 0;
-        {
-            // slots tid, tid + B, ... of the block (compile-time expanded)
-            TileLoad<N, CT, C, T> tl(a, cur, 0);
-            uint4 pre[PERB];
-#pragma unroll
-            for (int q = 0; q < PERB; ++q) {
-                const int sl = q * B + tid;
-                const int row = sl / G::CH;
-                const int ch = sl - row * G::CH;
-                const int r0 = row / G::R;
-                const int r1 = row - r0 * G::R;
-                const bool ok = sl < G::SLOTS && r0 < tl.lim0 && r1 < tl.lim1;
-                pre[q] = tl.g[ok ? r0 * tl.p0v + r1 * tl.p1v + ch : 0];
-            }
-#pragma unroll
-            for (int q = 0; q < PERB; ++q) tile_v[q * B + tid] = pre[q];
-        }
-        lds_barrier();
-        for (uint32_t j0 = 0; j0 < count; j0 += uint32_t(stride)) {
-            // a wavefront without any particle in this round skips it (uniform);
-            // inside a working wavefront, lanes past the end evaluate the tile's
-            // first particle and store nothing
-            if (j0 + uint32_t((pair ? 32 : 64) * (tid / 64)) >= count) continue;
-            const uint32_t j = j0 + jlane;
-            const bool active = j < count;
-            const uint32_t jj = start + (active ? j : 0u);
-            const long p = long(a.perm[jj]);
-            const double x[3] = {a.pos_sorted[3 * long(jj)], a.pos_sorted[3 * long(jj) + 1],
-                                 a.pos_sorted[3 * long(jj) + 2]};
-            int cell[3];
-            AT w[3][N], wd[3][N];
-            particle_setup_x<N, AT>(a, x, cell, w, wd);  // finite by construction of the bucket
-            const CT* base = tile + ((cell[0] - o0) * G::R + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * C;
-            auto rows = [base](int ia, int ib) { return base + (ia * G::R + ib) * G::LROW; };
-            if (pair) {
-                // both lanes of a pair run the same instructions: lane `half`
-                // takes planes half*N/2 .. half*N/2 + N/2 - 1
-                const int ia0 = half * (N / 2);
-                AT w0s[N / 2], wd0s[N / 2];
-#pragma unroll
-                for (int k = 0; k < N / 2; ++k) {
-                    w0s[k] = half ? w[0][N / 2 + k] : w[0][k];
-                    wd0s[k] = half ? wd[0][N / 2 + k] : wd[0][k];
-                }
-                Partial<AT, C> mine, other;
-                contract_planes<N, CT, AT, C, GRAD, N / 2, true>(
-                    w0s, wd0s, w, wd, [&](int k, int ib) { return rows(ia0 + k, ib); }, mine);
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    other.u[c] = shfl_xor1(mine.u[c]);
-                    other.g0[c] = shfl_xor1(mine.g0[c]);
-                    other.g1[c] = shfl_xor1(mine.g1[c]);
-                    other.g2[c] = shfl_xor1(mine.g2[c]);
-                }
-                if (active && half == 0) store_sum<AT, C, GRAD>(a, p, mine, other);
-            } else {
-                Partial<AT, C> lo, hi;
-                contract_planes<N, CT, AT, C, GRAD, N / 2, true>(w[0], wd[0], w, wd, rows, lo);
-                contract_planes<N, CT, AT, C, GRAD, N / 2, true>(
-                    w[0] + N / 2, wd[0] + N / 2, w, wd, [&](int k, int ib) { return rows(N / 2 + k, ib); },
-                    hi);
-                if (active) store_sum<AT, C, GRAD>(a, p, lo, hi);
-            }
-        }
-        lds_barrier();
-    }
+    for (uint32_t cur = next_tile(a, b0, b1); cur < b1; cur = next_tile(a, cur + 1, b1))
+        tile_eval<N, CT, C, GRAD, T, B>(a, cur, tile_v);
 }
 
 // ------------------------------------------------------------- launchers ---
