@@ -208,6 +208,64 @@ void bsi_batch_destroy(bsi_batch* batch);
 /* One-shot: create, run without a graph, synchronise `hip_stream`, destroy. */
 bsi_status bsi_eval_batch(bsi_ctx* ctx, const bsi_eval_item* items, int32_t count, void* hip_stream);
 
+/* ---- serving: resident fields, continuous batching of particle queries --- */
+
+typedef struct bsi_server_config {
+    size_t hbm_budget;       /* device bytes for requests in flight (positions, outputs and
+                                binning scratch), allocated once at creation             */
+    int32_t max_slots;       /* requests on the GPU at once, one HIP stream each (1..64) */
+    int32_t queue_capacity;  /* waiting requests before bsi_server_submit says BSI_E_BUSY */
+    int32_t reserved[4];     /* must be 0 */
+} bsi_server_config;
+
+typedef struct bsi_server_stats {
+    int64_t completed;       /* requests finished successfully since the last reset      */
+    int64_t failed;          /* requests that ended with an error                        */
+    double p50_ns, p99_ns;   /* latency from submit to outputs in host memory            */
+    double device_p50_ns, device_p99_ns;  /* first copy in to last copy out, on the GPU  */
+    int64_t points;          /* particles of the completed requests                      */
+    double points_per_s;     /* points / (last completion - first submit)                */
+    int64_t max_inflight;    /* most requests on the GPU at once                         */
+    size_t peak_arena_bytes; /* most arena bytes held at once                            */
+} bsi_server_report;
+
+/* Start a server on `ctx`: a device arena of cfg->hbm_budget bytes, max_slots
+ * HIP streams (default priority) and one scheduler thread that owns all of
+ * the server's GPU work.  Requests are admitted in arrival order as soon as a
+ * slot is free and the arena holds the request's buffers; each admitted
+ * request copies its positions in, runs the binned gather of its field (the
+ * configuration bsi_ctx_lookup_config gives for its size) and copies u (and
+ * grad) out on its slot's stream, so requests overlap on the device and a
+ * request's result is bitwise the result of bsi_eval_ex on the same field
+ * with that configuration, whatever else runs.  While a server runs, use its
+ * context from other threads only after bsi_server_drain.  BSI_E_NOMEM if the
+ * arena does not fit. */
+bsi_status bsi_server_create(bsi_ctx* ctx, const bsi_server_config* cfg, bsi_server** out);
+/* Make `field` (a field of the server's context, prefiltered by the caller)
+ * servable under `field_id`.  The field must outlive the server. */
+bsi_status bsi_server_add_field(bsi_server* server, int32_t field_id, bsi_field* field);
+/* Queue a request: P (1 <= P < 2^31) positions pos_host [P][3] FP64, outputs
+ * u_host [P][ncomp] and grad_host [P][ncomp][3] (or NULL) in host memory, in
+ * the field's output type.  Host buffers should be pinned (hipHostMalloc) so
+ * that copies overlap; they belong to the caller and must stay valid until
+ * the request completes.  Returns a ticket.  BSI_E_NOMEM if the request alone
+ * needs more than the arena, BSI_E_BUSY if the queue is full, BSI_E_INVAL for
+ * an unknown field id. */
+bsi_status bsi_server_submit(bsi_server* server, int32_t field_id, const double* pos_host, int64_t P,
+                             void* u_host, void* grad_host, uint64_t* ticket);
+/* *done = 1 once the request has completed (its outputs are in host memory);
+ * the return value is then the request's own status.  latency_ns may be NULL. */
+bsi_status bsi_server_poll(bsi_server* server, uint64_t ticket, int32_t* done, int64_t* latency_ns);
+/* Block until the request completes; returns its status. */
+bsi_status bsi_server_wait(bsi_server* server, uint64_t ticket, int64_t* latency_ns);
+/* Block until every submitted request has completed. */
+bsi_status bsi_server_drain(bsi_server* server);
+/* Latency percentiles and throughput of the requests completed since the last reset. */
+bsi_status bsi_server_stats(bsi_server* server, bsi_server_report* out);
+bsi_status bsi_server_reset_stats(bsi_server* server);
+/* Finish every submitted request, stop the scheduler and free the server. */
+void bsi_server_destroy(bsi_server* server);
+
 /* ---- autotuning ------------------------------------------------------------- */
 
 /* Time the candidate configurations of the evaluation (LDS-tiled gather with

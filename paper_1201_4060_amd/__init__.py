@@ -12,7 +12,7 @@ torch is used for device memory and streams only.
 from . import _bsi
 from ._bsi import (BsiError, BSI_F64, BSI_F32, BSI_BF16, BSI_PREFILTER_L2OPT,
                    BSI_PREFILTER_INTERP, EvalConfig)
-from .api import Batch, Context, Field
+from .api import Batch, Context, Field, Server
 
 __all__ = ["_bsi", "BsiError", "BSI_F64", "BSI_F32", "BSI_BF16", "BSI_PREFILTER_L2OPT",
-           "BSI_PREFILTER_INTERP", "EvalConfig", "Batch", "Context", "Field"]
+           "BSI_PREFILTER_INTERP", "EvalConfig", "Batch", "Context", "Field", "Server"]

@@ -33,6 +33,22 @@ class EvalConfig(ctypes.Structure):
                 ("tiles_per_group", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class ServerReport(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("p50_ns", ctypes.c_double), ("p99_ns", ctypes.c_double),
+                ("device_p50_ns", ctypes.c_double), ("device_p99_ns", ctypes.c_double),
+                ("points", ctypes.c_int64), ("points_per_s", ctypes.c_double),
+                ("max_inflight", ctypes.c_int64), ("peak_arena_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class EvalItem(ctypes.Structure):
     _fields_ = [("field", ctypes.c_void_p), ("pos", ctypes.c_void_p), ("P", ctypes.c_int64),
                 ("u", ctypes.c_void_p), ("grad", ctypes.c_void_p)]
@@ -89,6 +105,15 @@ SIGNATURES = {
                       ctypes.POINTER(ctypes.c_double)]),
     "bsi_ctx_load_tuning": (ST, [VP, ctypes.c_char_p]),
     "bsi_ctx_lookup_config": (ST, [VP, VP, I64, ctypes.POINTER(EvalConfig)]),
+    "bsi_server_create": (ST, [VP, ctypes.POINTER(ServerConfig), ctypes.POINTER(VP)]),
+    "bsi_server_add_field": (ST, [VP, I32, VP]),
+    "bsi_server_submit": (ST, [VP, I32, VP, I64, VP, VP, ctypes.POINTER(ctypes.c_uint64)]),
+    "bsi_server_poll": (ST, [VP, ctypes.c_uint64, ctypes.POINTER(I32), ctypes.POINTER(I64)]),
+    "bsi_server_wait": (ST, [VP, ctypes.c_uint64, ctypes.POINTER(I64)]),
+    "bsi_server_drain": (ST, [VP]),
+    "bsi_server_stats": (ST, [VP, ctypes.POINTER(ServerReport)]),
+    "bsi_server_reset_stats": (ST, [VP]),
+    "bsi_server_destroy": (None, [VP]),
     "bsi_fill_uniform_positions": (ST, [VP, ctypes.c_uint64, I64, ctypes.POINTER(ctypes.c_double), VP, VP]),
 }
 
@@ -279,3 +304,54 @@ def bsi_fill_uniform_positions(ctx, seed, P, length, pos, stream=None):
     L = (ctypes.c_double * 3)(*length)
     _check(lib().bsi_fill_uniform_positions(ctx, seed, P, L, _ptr(pos), stream),
            "bsi_fill_uniform_positions")
+
+
+def bsi_server_create(ctx, hbm_budget, max_slots, queue_capacity=1 << 20):
+    cfg = ServerConfig()
+    cfg.hbm_budget, cfg.max_slots, cfg.queue_capacity = hbm_budget, max_slots, queue_capacity
+    out = VP()
+    _check(lib().bsi_server_create(ctx, ctypes.byref(cfg), ctypes.byref(out)), "bsi_server_create")
+    return out.value
+
+
+def bsi_server_add_field(server, field_id, field):
+    _check(lib().bsi_server_add_field(server, field_id, field), "bsi_server_add_field")
+
+
+def bsi_server_submit(server, field_id, pos_host, P, u_host, grad_host=None):
+    t = ctypes.c_uint64()
+    _check(lib().bsi_server_submit(server, field_id, _ptr(pos_host), P, _ptr(u_host), _ptr(grad_host),
+                                   ctypes.byref(t)), "bsi_server_submit")
+    return t.value
+
+
+def bsi_server_poll(server, ticket):
+    """(done, latency_ns); raises the request's own error once it is done."""
+    d = I32()
+    lat = I64()
+    _check(lib().bsi_server_poll(server, ticket, ctypes.byref(d), ctypes.byref(lat)), "bsi_server_poll")
+    return bool(d.value), lat.value
+
+
+def bsi_server_wait(server, ticket):
+    lat = I64()
+    _check(lib().bsi_server_wait(server, ticket, ctypes.byref(lat)), "bsi_server_wait")
+    return lat.value
+
+
+def bsi_server_drain(server):
+    _check(lib().bsi_server_drain(server), "bsi_server_drain")
+
+
+def bsi_server_stats(server):
+    r = ServerReport()
+    _check(lib().bsi_server_stats(server, ctypes.byref(r)), "bsi_server_stats")
+    return r.as_dict()
+
+
+def bsi_server_reset_stats(server):
+    _check(lib().bsi_server_reset_stats(server), "bsi_server_reset_stats")
+
+
+def bsi_server_destroy(server):
+    lib().bsi_server_destroy(server)

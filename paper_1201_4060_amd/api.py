@@ -152,3 +152,66 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Server:
+    """bsi_server: resident fields served to particle-query requests.
+
+    Host tensors passed to submit() must be CPU tensors (pinned for overlap);
+    they are kept referenced here until the request is waited for.
+    """
+
+    def __init__(self, ctx, hbm_budget, max_slots, queue_capacity=1 << 20):
+        self.ctx = ctx
+        self.handle = _bsi.bsi_server_create(ctx.handle, hbm_budget, max_slots, queue_capacity)
+        self.fields = {}
+        self._keep = {}
+
+    def add_field(self, field_id, field):
+        _bsi.bsi_server_add_field(self.handle, field_id, field.handle)
+        self.fields[field_id] = field
+
+    def submit(self, field_id, pos, u, grad=None):
+        f = self.fields[field_id]
+        assert not pos.is_cuda and pos.is_contiguous() and pos.dtype == torch.float64
+        P = pos.shape[0]
+        assert u.shape == (P, f.ncomp) and u.dtype == f.out_dtype and not u.is_cuda and u.is_contiguous()
+        if grad is not None:
+            assert grad.shape == (P, f.ncomp, 3) and grad.dtype == f.out_dtype and not grad.is_cuda
+            assert grad.is_contiguous()
+        t = _bsi.bsi_server_submit(self.handle, field_id, pos, P, u, grad)
+        self._keep[t] = (pos, u, grad)
+        return t
+
+    def wait(self, ticket):
+        try:
+            return _bsi.bsi_server_wait(self.handle, ticket)
+        finally:
+            self._keep.pop(ticket, None)
+
+    def poll(self, ticket):
+        done, lat = _bsi.bsi_server_poll(self.handle, ticket)
+        if done:
+            self._keep.pop(ticket, None)
+        return done, lat
+
+    def drain(self):
+        _bsi.bsi_server_drain(self.handle)
+
+    def stats(self):
+        return _bsi.bsi_server_stats(self.handle)
+
+    def reset_stats(self):
+        _bsi.bsi_server_reset_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            _bsi.bsi_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

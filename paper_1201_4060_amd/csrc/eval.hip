@@ -245,8 +245,22 @@ bool tiled_supported(const bsi_field* f, int tile) {
     return tile_ok_ct<uint16_t>(f->N, f->C, tile);
 }
 
-bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
-                    const bsi_eval_config& cfg, hipStream_t s) {
+// Sort tile actually used: at least n/256 cells per tile edge, so that the
+// bucket table has at most 2^24 entries.
+static int effective_tile(const bsi_field* f, const bsi_eval_config& cfg) {
+    if (cfg.sort_tile <= 0) return 0;
+    const int nmax = std::max(f->n[0], std::max(f->n[1], f->n[2]));
+    return std::max(cfg.sort_tile, (nmax + 255) / 256);
+}
+
+size_t eval_ws_bytes(const bsi_field* f, int64_t P, const bsi_eval_config& cfg) {
+    const int tile = effective_tile(f, cfg);
+    if (tile == 0 || P == 0) return 0;
+    return 3 * size_t(P) * sizeof(double) + size_t(P) * sizeof(uint32_t) + bin_scratch_bytes(f, P, tile);
+}
+
+bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
+                       const bsi_eval_config& cfg, hipStream_t s, void* ws) {
     if (P == 0) return BSI_OK;
     int block = cfg.block > 0 ? cfg.block : 256;
     BSI_CHECK(block % 64 == 0 && block >= 64 && block <= 256, BSI_E_INVAL,
@@ -255,16 +269,10 @@ bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* g
     const double* pos_sorted = nullptr;
     const uint32_t* hist = nullptr;
     const uint32_t* offs = nullptr;
-    int tile = cfg.sort_tile;
+    const int tile = effective_tile(f, cfg);
     size_t nbf = 0;
     if (tile > 0) {
-        // keep the bucket table at most 2^24 entries
-        const int nmax = std::max(f->n[0], std::max(f->n[1], f->n[2]));
-        tile = std::max(tile, (nmax + 255) / 256);
-        const size_t possz = 3 * size_t(P) * sizeof(double);
-        const size_t need = possz + size_t(P) * sizeof(uint32_t) + bin_scratch_bytes(f, P, tile);
-        void* ws = nullptr;
-        BSI_TRY(get_workspace(f->ctx->eval_ws, s, need, &ws));
+        BSI_CHECK(ws != nullptr, BSI_E_INVAL, "binned evaluation needs a workspace");
         double* ps = static_cast<double*>(ws);
         uint32_t* pm = reinterpret_cast<uint32_t*>(ps + 3 * size_t(P));
         BSI_TRY(bin_run(f, pos, P, tile, pm, pm + P, ps, s));
@@ -315,6 +323,15 @@ bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* g
     }
     BSI_HIP(hipGetLastError());
     return BSI_OK;
+}
+
+bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
+                    const bsi_eval_config& cfg, hipStream_t s) {
+    if (P == 0) return BSI_OK;
+    void* ws = nullptr;
+    const size_t need = eval_ws_bytes(f, P, cfg);
+    if (need) BSI_TRY(get_workspace(f->ctx->eval_ws, s, need, &ws));
+    return eval_run_ws(f, pos, P, u, grad, cfg, s, ws);
 }
 
 bsi_status debug_cells_run(bsi_field* f, const double* pos, int64_t P, int32_t* cell, double* t,
