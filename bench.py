@@ -1,13 +1,23 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the B-spline interpolation hot path on one MI355X.
 
-Workload: a 256^3 three-component divergence-free Kolmogorov field (spectrum
-|uhat|^2 ~ k^-11/3, cut-off |k| <= n/3, complex128 input), FP32 coefficient
-grid, spline orders 4 and 6, 10^6 uniform particles.  One step runs the whole
-path for each order: prefilter (FP64 symbol multiply + inverse 3D real FFT)
-then evaluation (cell/Morton binning + gather) of u and grad u at every
-particle.  value = interpolated points (particles x orders) per second of
-whole step, inputs resident in HBM.
+Default workload (--form plain): a 256^3 three-component divergence-free
+Kolmogorov field (spectrum |uhat|^2 ~ k^-11/3, cut-off |k| <= n/3, complex128
+input), FP32 coefficient grid, spline orders 4 and 6, 10^6 uniform particles.
+One step runs the whole path for each order: prefilter (FP64 symbol multiply +
+inverse 3D real FFT) then evaluation (cell/Morton binning + gather) of u and
+grad u at every particle.  value = interpolated points (particles x orders)
+per second of whole step, inputs resident in HBM.
+
+Other forms (one JSON line each, same keys):
+  --form precision  512^3 x3 field, order 6, FP32 and BF16 grids, 10^7
+                    clustered particles; errors against the FP64 oracle
+  --form batch      64 fields (n in {64,128,192,256}, order 4|6, 10^3..10^6
+                    particles each) in one persistent gather launch replayed
+                    from a HIP graph; beside it one launch per field
+  --form serve      resident 1024^3 and 256^3 fields (both orders), Poisson
+                    particle-query requests; points/s with p50/p99 latency
+  --form copy       1 GiB device copy (calibrates HBM byte counters)
 
 Prints one JSON line on stdout; diagnostics go to stderr.
 """
@@ -30,53 +40,56 @@ ORDERS = (4, 6)
 P = 1_000_000
 FIELD_SEED, POS_SEED = 1, 101
 STAGES = ("fft_axis0", "fft_axis1", "fft_c2r", "bin_count", "bin_scan", "bin_scatter", "gather")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256cube_x3_f32_orders4_6_1e6.md")
+KERNEL_SOURCES = {"gather": ["eval.hip", "gather.hpp", "common.hpp"], "fft": ["fft.hip", "common.hpp"]}
 
 
 def eprint(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def distinct_stencil_points(pos, n, order):
-    """Number of distinct grid points in the union of all particles' stencils."""
-    h = 2.0 * np.pi / n
-    cell = np.mod(np.floor(pos * (n / (2.0 * np.pi))).astype(np.int64), n)
-    mark = np.zeros(n * n * n, dtype=bool)
-    offs = np.arange(order) - order // 2 + 1
-    for a in offs:
-        i0 = np.mod(cell[:, 0] + a, n) * n * n
-        for b in offs:
-            i01 = i0 + np.mod(cell[:, 1] + b, n) * n
-            for e in offs:
-                mark[i01 + np.mod(cell[:, 2] + e, n)] = True
-    del h
-    return int(mark.sum())
+# ------------------------------------------------------------ byte counts ---
 
+def distinct_stencil_points(pos, n, order, mark=None):
+    """Number of distinct grid points in the union of all particles' stencils.
 
-def algorithmic_bytes(stage, order, U):
-    """Algorithmic HBM bytes of one launch of `stage` for this workload.
-
-    gather      : positions (24 B) + u and grad u in FP32 (16 B * C) per particle,
-                  plus every distinct coefficient touched once (C * 4 B per point)
-    fft_axis0   : read the complex128 spectrum, write the complex64 work array
-    fft_axis1   : read and write the complex64 work array
-    fft_c2r     : read the work array, write the ghost-padded FP32 grid
+    pos: torch float64 device tensor [P][3] on [0, 2pi)^3 (or numpy array).
+    Counted on the device with a mark array of n^3 booleans.
     """
-    n, C = N_GRID, NCOMP
+    import torch
+    if isinstance(pos, np.ndarray):
+        pos = torch.from_numpy(pos).cuda()
+    cell = torch.remainder(torch.floor(pos * (n / (2.0 * np.pi))).to(torch.int64), n)
+    if mark is None or mark.numel() != n ** 3:
+        mark = torch.zeros(n ** 3, dtype=torch.bool, device=pos.device)
+    else:
+        mark.zero_()
+    offs = [o - order // 2 + 1 for o in range(order)]
+    for a in offs:
+        i0 = torch.remainder(cell[:, 0] + a, n) * (n * n)
+        for b in offs:
+            i01 = i0 + torch.remainder(cell[:, 1] + b, n) * n
+            for e in offs:
+                mark[i01 + torch.remainder(cell[:, 2] + e, n)] = True
+    return int(mark.sum().item())
+
+
+def gather_bytes(P_, C, U, coef_bytes, out_bytes=4):
+    """Algorithmic bytes of one gather: positions (24 B) and u, grad u per
+    particle, plus every distinct coefficient touched once."""
+    return P_ * (24 + 4 * C * out_bytes) + U * C * coef_bytes
+
+
+def fft_bytes(stage, n, C, order, spec_bytes=16, work_bytes=8, grid_bytes=4):
+    """Algorithmic bytes of one FFT pass (spectrum read, work array, grid written)."""
     half = n * n * (n // 2 + 1) * C
-    padded = (n + order - 1) ** 3 * C
-    if stage == "gather":
-        return P * (24 + 16 * C) + U * C * 4
     if stage == "fft_axis0":
-        return half * (16 + 8)
+        return half * (spec_bytes + work_bytes)
     if stage == "fft_axis1":
-        return half * 16
+        return half * 2 * work_bytes
     if stage == "fft_c2r":
-        return half * 8 + padded * 4
+        return half * work_bytes + (n + order - 1) ** 3 * C * grid_bytes
     return None
-
-
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256cube_x3_f32_orders4_6_1e6.md")
-KERNEL_SOURCES = {"gather": ["eval.hip", "gather.hpp", "common.hpp"], "fft": ["fft.hip", "common.hpp"]}
 
 
 def measured_traffic(key):
@@ -95,7 +108,7 @@ def measured_traffic(key):
     if line is None:
         return None
     table = json.loads(line.split(":", 1)[1])
-    ent = table.get(key) or table.get(key.split("@N")[0])
+    ent = table.get(key) or table.get(key.split("@")[0])
     if ent is None:
         return None
     kind = "gather" if key.startswith("gather") else "fft"
@@ -106,7 +119,63 @@ def measured_traffic(key):
     return ent["traffic_bytes"] if h.hexdigest()[:16] == ent["src"] else None
 
 
-def cpu_baseline(uhat, pos, sample):
+def roofline_entry(key, alg, avg_us, traffic=None):
+    achieved = alg / (avg_us * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": key,
+            "algorithmic_bytes": int(alg), "avg_us": round(avg_us, 2)}
+
+
+# ---------------------------------------------------------------- timing ---
+
+def read_stages(bsi, ctx, suffix, names=STAGES):
+    out = {}
+    for st in names:
+        ms, cnt = bsi._bsi.bsi_ctx_read_timing(ctx.handle, st)
+        if cnt:
+            out[f"{st}@{suffix}"] = {"avg_us": 1000.0 * ms / cnt, "launches": cnt, "total_ms": ms}
+    return out
+
+
+def timed_steps(step, warmup, steps, ctxs, bsi):
+    """Run warm-up steps, then time `steps` steps (synchronised on both sides)
+    with per-stage kernel timing on every context; returns seconds/step."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    for c in ctxs:
+        bsi._bsi.bsi_ctx_reset_timing(c.handle)
+        bsi._bsi.bsi_ctx_set_timing(c.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) / steps
+
+
+def base_line(args, value, unit, sec_per_step, dtype, config, roofline, cpu, **extra):
+    line = {"metric": METRIC, "value": round(value, 1), "unit": unit, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec_per_step * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config, "roofline": roofline}
+    line.update(extra)
+    line["cpu_baseline"] = cpu
+    return line
+
+
+def print_stages(stages, sec_per_step, steps):
+    tot = sum(v["total_ms"] for v in stages.values()) / steps
+    eprint(f"{sec_per_step * 1e3:.3f} ms/step wall, {tot:.3f} ms/step in library kernels")
+    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["total_ms"]):
+        eprint(f"  {k:22s} {v['avg_us']:9.1f} us x {v['launches']}")
+
+
+# ------------------------------------------------------------ plain form ---
+
+def cpu_baseline_plain(uhat, pos, sample):
     """Time the FP64 oracle (as it stands) on a bounded sample of the workload."""
     from threadpoolctl import threadpool_limits
     import oracle
@@ -128,6 +197,410 @@ def cpu_baseline(uhat, pos, sample):
             "sample": (f"full FP64 prefilter of the 256^3x3 field per order + evaluation of "
                        f"{sample} of the 1e6 particles per order, scaled to 1e6; numpy, one thread")}
 
+
+def form_plain(args):
+    import torch
+    import synth
+    import paper_1201_4060_amd as bsi
+    dev = torch.device("cuda:0")
+    eprint("generating inputs ...")
+    uhat_np = synth.kolmogorov_spectrum(N_GRID, NCOMP, seed=FIELD_SEED)
+    pos_np = synth.uniform_positions(P, seed=POS_SEED)
+    uhat = torch.from_numpy(uhat_np).to(dev)
+    pos = torch.from_numpy(pos_np).to(dev)
+
+    ctxs = {o: bsi.Context(0) for o in ORDERS}          # one context per order: per-order stage timing
+    fields = {o: bsi.Field(ctxs[o], N_GRID, NCOMP, o, bsi.BSI_F32) for o in ORDERS}
+    outs = {o: (torch.empty((P, NCOMP), dtype=torch.float32, device=dev),
+                torch.empty((P, NCOMP, 3), dtype=torch.float32, device=dev)) for o in ORDERS}
+    cfg = None
+    if args.sort_tile is not None:
+        cfg = bsi.EvalConfig(sort_tile=args.sort_tile, block=256, xcd_remap=1)
+
+    def step():
+        for o in ORDERS:
+            fields[o].set_spectrum(uhat)
+            fields[o].eval(pos, cfg=cfg, out=outs[o])
+
+    sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi)
+    stages = {}
+    for o in ORDERS:
+        stages.update(read_stages(bsi, ctxs[o], f"N{o}"))
+        bsi._bsi.bsi_ctx_set_timing(ctxs[o].handle, False)
+    print_stages(stages, sps, args.steps)
+
+    U = {o: distinct_stencil_points(pos, N_GRID, o) for o in ORDERS}
+    alg = {}
+    for k in stages:
+        st, o = k.split("@N")
+        o = int(o)
+        alg[k] = gather_bytes(P, NCOMP, U[o], 4) if st == "gather" else fft_bytes(st, N_GRID, NCOMP, o)
+    # dominant kernel: largest share of the step among those with a byte count
+    dom = max((k for k in stages if alg[k] is not None), key=lambda k: stages[k]["total_ms"])
+    roofline = roofline_entry(dom, alg[dom], stages[dom]["avg_us"], measured_traffic(dom))
+    gather_rl = {}
+    for o in ORDERS:
+        k = f"gather@N{o}"
+        if k in stages:
+            e = roofline_entry(k, alg[k], stages[k]["avg_us"])
+            gather_rl[k] = {"achieved_GBs": e["achieved"], "frac": e["frac"], "algorithmic_bytes": alg[k],
+                            "distinct_points": U[o], "avg_us": e["avg_us"],
+                            "points_per_s": round(P / (stages[k]["avg_us"] * 1e-6), 1)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        eprint("timing the CPU oracle on a sample ...")
+        cpu = cpu_baseline_plain(uhat_np, pos_np, args.cpu_sample)
+    for o in ORDERS:
+        fields[o].close()
+        ctxs[o].close()
+    config = {"workload": "256^3 x3 divergence-free Kolmogorov field, FP32 grid, orders 4 and 6, "
+                          "1e6 uniform particles; step = prefilter + eval per order",
+              "n": N_GRID, "ncomp": NCOMP, "orders": list(ORDERS), "particles": P,
+              "grid_dtype": "f32", "spectrum_dtype": "c128", "parallelism": "single GPU"}
+    return base_line(args, len(ORDERS) * P / sps, "points/s", sps, "f32", config, roofline, cpu,
+                     gather_roofline=gather_rl,
+                     stages_us={k: round(v["avg_us"], 2) for k, v in stages.items()})
+
+
+# -------------------------------------------------------- precision form ---
+
+def form_precision(args):
+    """512^3 x3 field, order 6, FP32 and BF16 coefficient grids, 10^7 clustered
+    particles (5e6 uniform + 100 Gaussian blobs of 5e4, sigma 0.1)."""
+    import torch
+    from threadpoolctl import threadpool_limits
+    import synth
+    import oracle
+    import paper_1201_4060_amd as bsi
+    n, C, N, Pp = 512, 3, 6, 10_000_000
+    dev = torch.device("cuda:0")
+    eprint("generating the 512^3 spectrum and 1e7 clustered particles ...")
+    uhat_np = synth.kolmogorov_spectrum(n, C, seed=2)
+    pos_np = synth.clustered_positions(5_000_000, 100, 50_000, 0.1, seed=102)
+    uhat = torch.from_numpy(uhat_np).to(dev)
+    pos = torch.from_numpy(pos_np).to(dev)
+    kinds = (("f32", bsi.BSI_F32, 4), ("bf16", bsi.BSI_BF16, 2))
+    ctxs = {k: bsi.Context(0) for k, _, _ in kinds}
+    fields = {k: bsi.Field(ctxs[k], n, C, N, dt) for k, dt, _ in kinds}
+    outs = {k: (torch.empty((Pp, C), dtype=torch.float32, device=dev),
+                torch.empty((Pp, C, 3), dtype=torch.float32, device=dev)) for k, _, _ in kinds}
+
+    def step():
+        for k, _, _ in kinds:
+            fields[k].set_spectrum(uhat)
+            fields[k].eval(pos, out=outs[k])
+
+    sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi)
+    stages = {}
+    for k, _, _ in kinds:
+        stages.update(read_stages(bsi, ctxs[k], k))
+        bsi._bsi.bsi_ctx_set_timing(ctxs[k].handle, False)
+    print_stages(stages, sps, args.steps)
+    U = distinct_stencil_points(pos, n, N)
+    cbytes = {k: cb for k, _, cb in kinds}
+    alg = {}
+    for key in stages:
+        st, k = key.split("@")
+        alg[key] = gather_bytes(Pp, C, U, cbytes[k]) if st == "gather" else fft_bytes(st, n, C, N)
+    dom = max((k for k in stages if alg[k] is not None), key=lambda k: stages[k]["total_ms"])
+    roofline = roofline_entry(dom, alg[dom], stages[dom]["avg_us"])
+    per = {}
+    for k, _, cb in kinds:
+        g = stages[f"gather@{k}"]
+        e = roofline_entry(f"gather@{k}", alg[f"gather@{k}"], g["avg_us"])
+        per[k] = {"gather_us": e["avg_us"], "gather_achieved_GBs": e["achieved"], "gather_frac": e["frac"],
+                  "gather_points_per_s": round(Pp / (g["avg_us"] * 1e-6), 1),
+                  "grid_bytes": fields[k].nbytes()}
+    # errors against the FP64 oracle on a sample (outside the timed region);
+    # the same oracle work is the CPU baseline
+    eprint("FP64 oracle on a sample ...")
+    sample = np.sort(np.random.default_rng(1).choice(Pp, args.cpu_sample_precision, replace=False))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        grid = oracle.prefilter(uhat_np, N)
+        t1 = time.perf_counter()
+        want_u, want_g = oracle.evaluate(grid, pos_np[sample], N)
+        t2 = time.perf_counter()
+    umax = float(np.abs(grid).max())
+    del grid
+    S6 = 115.0 / 96.0  # max_t sum_j |w'_j(t)| of the order-6 derivative weights
+    idx = torch.from_numpy(sample).to(dev)
+    for k, _, _ in kinds:
+        u = outs[k][0][idx].double().cpu().numpy()
+        g = outs[k][1][idx].double().cpu().numpy()
+        errs = {}
+        for name, got, want in (("u", u, want_u), ("grad", g, want_g)):
+            got = got.reshape(got.shape[0], -1)
+            want = want.reshape(want.shape[0], -1)
+            scale = np.abs(want).max(axis=0)
+            d = np.abs(got - want)
+            pointwise = d / np.maximum(np.abs(want), 1e-3 * scale)
+            errs[name] = {"max_rel": float((d.max(axis=0) / scale).max()),
+                          "rms_rel": float((np.sqrt((d ** 2).mean(axis=0)) /
+                                            np.sqrt((want ** 2).mean(axis=0))).max()),
+                          "p99_pointwise_rel": float(np.percentile(pointwise, 99))}
+        if k == "bf16":
+            errs["bound_u_abs"] = 2.0 ** -8 * umax
+            errs["bound_grad_abs"] = 2.0 ** -8 * umax * S6 * n / (2 * np.pi)
+            errs["max_abs_u"] = float(np.abs(u - want_u).max())
+            errs["max_abs_grad"] = float(np.abs(g - want_g).max())
+        per[k]["error_vs_fp64_oracle"] = errs
+        eprint(f"  {k}: {json.dumps(errs)}")
+    cpu = {"value": Pp / ((t1 - t0) + (t2 - t1) * Pp / len(sample)), "unit": "points/s", "cores": 1,
+           "kind": "oracle",
+           "sample": (f"FP64 prefilter of the 512^3x3 field ({t1 - t0:.1f} s) + evaluation of "
+                      f"{len(sample)} of the 1e7 particles ({t2 - t1:.1f} s), scaled to 1e7 particles "
+                      f"for one grid; numpy, one thread")}
+    for k, _, _ in kinds:
+        fields[k].close()
+        ctxs[k].close()
+    config = {"workload": "512^3 x3 divergence-free Kolmogorov field, order 6, FP32 and BF16 coefficient "
+                          "grids (FP32 accumulation), 1e7 clustered particles (5e6 uniform + 100 Gaussian "
+                          "blobs sigma 0.1); step = prefilter + eval per grid type",
+              "n": n, "ncomp": C, "order": N, "particles": Pp, "grid_dtypes": ["f32", "bf16"],
+              "parallelism": "single GPU"}
+    return base_line(args, 2 * Pp / sps, "points/s", sps, "f32", config, roofline, cpu, per_grid_dtype=per,
+                     stages_us={k: round(v["avg_us"], 2) for k, v in stages.items()})
+
+
+# ------------------------------------------------------------ batch form ---
+
+def batch_specs(count=64):
+    """Field f: n uniform over {64,128,192,256}, order uniform over {4,6},
+    P = round(10^U(3,6)); draws from stream 13 of seed 300+f."""
+    from synth.rng import keyed_uniform
+    specs = []
+    for f in range(count):
+        u = keyed_uniform(300 + f, 13, np.arange(3))
+        n = (64, 128, 192, 256)[min(int(u[0] * 4), 3)]
+        N = (4, 6)[min(int(u[1] * 2), 1)]
+        Pf = int(round(10 ** (3 + 3 * u[2])))
+        specs.append((n, N, Pf))
+    return specs
+
+
+def form_batch(args):
+    import torch
+    from threadpoolctl import threadpool_limits
+    import synth
+    import oracle
+    import paper_1201_4060_amd as bsi
+    dev = torch.device("cuda:0")
+    specs = batch_specs()
+    ctx = bsi.Context(0)
+    fields, items = [], []
+    eprint("building 64 fields ...")
+    spec_buf = {}
+    for f, (n, N, Pf) in enumerate(specs):
+        if n not in spec_buf:
+            spec_buf[n] = torch.empty((3, n, n, n // 2 + 1), dtype=torch.complex128, device=dev)
+        bsi._bsi.bsi_synth_kolmogorov(ctx.handle, n, 3, 300 + f, spec_buf[n])
+        fld = bsi.Field(ctx, n, 3, N, bsi.BSI_F32)
+        fld.set_spectrum(spec_buf[n])
+        pos = torch.from_numpy(synth.uniform_positions(Pf, seed=400 + f)).to(dev)
+        u = torch.empty((Pf, 3), dtype=torch.float32, device=dev)
+        g = torch.empty((Pf, 3, 3), dtype=torch.float32, device=dev)
+        fields.append(fld)
+        items.append((fld, pos, u, g))
+    del spec_buf
+    torch.cuda.synchronize()
+    Ptot = sum(s[2] for s in specs)
+    eprint(f"{Ptot} particles in total; autotuning ...")
+    tuned = set()
+    t0 = time.perf_counter()
+    for (n, N, Pf), fld in zip(specs, fields):
+        key = (N, round(np.log2(Pf / n ** 3)))
+        if key not in tuned:
+            tuned.add(key)
+            bsi._bsi.bsi_tune(fld.handle, Pf, seed=len(tuned))
+    eprint(f"  {len(tuned)} tuning runs in {time.perf_counter() - t0:.1f} s")
+    batch = bsi.Batch(ctx, items)
+    modes = [batch.item_config(i) for i in range(len(items))]
+    n_tiled = sum(1 for c in modes if c.variant == 0)
+
+    sps = timed_steps(lambda: batch.run(use_graph=True), args.warmup, args.steps, [ctx], bsi)
+    graph = read_stages(bsi, ctx, "graph", ("batch_graph",))
+    # the same batch enqueued directly, for the per-kernel times
+    sps_eager = timed_steps(lambda: batch.run(use_graph=False), 1, args.steps, [ctx], bsi)
+    st_eager = read_stages(bsi, ctx, "batch", ("batch_bin", "batch_gather"))
+    # one launch sequence per field with the same configurations, for comparison
+    cfgs = [bsi._bsi.bsi_ctx_lookup_config(ctx.handle, fl.handle, it[1].shape[0])
+            for fl, it in zip(fields, items)]
+
+    def singles():
+        for (fl, pos, u, g), c in zip(items, cfgs):
+            fl.eval(pos, cfg=c, out=(u, g))
+
+    sps_single = timed_steps(singles, 1, args.steps, [ctx], bsi)
+    st_single = read_stages(bsi, ctx, "single", ("gather",))
+    bsi._bsi.bsi_ctx_set_timing(ctx.handle, False)
+    stages = {**graph, **st_eager, **st_single}
+    print_stages(stages, sps, args.steps)
+    eprint(f"graph {sps * 1e3:.3f} ms/step, direct {sps_eager * 1e3:.3f}, per-field launches "
+           f"{sps_single * 1e3:.3f}")
+    mark = torch.zeros(256 ** 3, dtype=torch.bool, device=dev)
+    alg = 0
+    for (n, N, Pf), (fl, pos, u, g) in zip(specs, items):
+        alg += gather_bytes(Pf, 3, distinct_stencil_points(pos, n, N, mark[: n ** 3]), 4)
+    del mark
+    roofline = roofline_entry("batch_gather", alg, stages["batch_gather@batch"]["avg_us"])
+    # CPU baseline: the oracle evaluating a sample of three fields (n = 64, 128, 192)
+    cpu = None
+    if not args.no_cpu_baseline:
+        eprint("timing the CPU oracle on a sample ...")
+        done, t_eval, pts = set(), 0.0, 0
+        with threadpool_limits(limits=1):
+            for f, (n, N, Pf) in enumerate(specs):
+                if n in done or n > 192:
+                    continue
+                done.add(n)
+                grid = oracle.prefilter(synth.kolmogorov_spectrum(n, 3, seed=300 + f), N)
+                m = min(Pf, 20000)
+                p = synth.uniform_positions(Pf, seed=400 + f)[:m]
+                t0 = time.perf_counter()
+                oracle.evaluate(grid, p, N)
+                t_eval += time.perf_counter() - t0
+                pts += m
+        cpu = {"value": pts / t_eval, "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": (f"oracle evaluation of {pts} particles of the first fields with n = 64, 128, "
+                          f"192 (grids from the oracle's prefilter, not timed); numpy, one thread")}
+    batch.close()
+    for fl in fields:
+        fl.close()
+    ctx.close()
+    config = {"workload": "64 divergence-free Kolmogorov fields, n uniform over {64,128,192,256}, order "
+                          "uniform over {4,6}, FP32 grids, 10^U(3,6) uniform particles each; step = one "
+                          "replay of the captured graph (binning + one persistent gather launch)",
+              "fields": len(specs), "particles": Ptot, "tiled_items": n_tiled,
+              "direct_items": len(specs) - n_tiled, "tuning_runs": len(tuned), "parallelism": "single GPU"}
+    return base_line(args, Ptot / sps, "points/s", sps, "f32", config, roofline, cpu,
+                     direct_enqueue_points_per_s=round(Ptot / sps_eager, 1),
+                     per_field_launches_points_per_s=round(Ptot / sps_single, 1),
+                     stages_us={k: round(v["avg_us"], 2) for k, v in stages.items()})
+
+
+# ------------------------------------------------------------ serve form ---
+
+def form_serve(args):
+    import torch
+    import synth
+    import paper_1201_4060_amd as bsi
+    from synth.rng import keyed_uniform
+    dev = torch.device("cuda:0")
+    big_n, n_big, small_n, n_small = (1024, 8, 256, 32) if args.serve_scale == "full" else (512, 2, 128, 8)
+    ctx = bsi.Context(0)
+    fields = {}
+    eprint(f"building {n_big} x {big_n}^3 + {n_small} x {small_n}^3 resident snapshots, orders 4 and 6 ...")
+    t0 = time.perf_counter()
+    snap = 0
+    for n, count, prec in ((big_n, n_big, torch.complex64), (small_n, n_small, torch.complex128)):
+        spec = torch.empty((3, n, n, n // 2 + 1), dtype=prec, device=dev)
+        for _ in range(count):
+            bsi._bsi.bsi_synth_kolmogorov(ctx.handle, n, 3, 500 + snap, spec)
+            for N in (4, 6):
+                fl = bsi.Field(ctx, n, 3, N, bsi.BSI_F32)
+                fl.set_spectrum(spec)
+                fields[2 * snap + (N == 6)] = fl
+            snap += 1
+            eprint(f"  snapshot {snap} ready ({time.perf_counter() - t0:.1f} s)")
+        del spec
+        torch.cuda.synchronize()
+        bsi._bsi.bsi_ctx_trim(ctx.handle)
+        torch.cuda.empty_cache()
+    resident = sum(f.nbytes() for f in fields.values())
+    eprint(f"{len(fields)} resident grids, {resident / 2**30:.1f} GiB")
+    # request positions: slices of a uniform and a clustered pool
+    pool_n = 2_000_000
+    pools = []
+    for p in (synth.uniform_positions(pool_n, seed=600),
+              synth.clustered_positions(pool_n // 2, 100, pool_n // 200, 0.1, seed=601)):
+        t = torch.empty((pool_n, 3), dtype=torch.float64, pin_memory=True)
+        t.numpy()[:] = p
+        pools.append(t)
+    nbuf = 48
+    maxp = 1_000_000
+    outs = [(torch.empty((maxp, 3), dtype=torch.float32, pin_memory=True),
+             torch.empty((maxp, 3, 3), dtype=torch.float32, pin_memory=True)) for _ in range(nbuf)]
+    nsnap = n_big + n_small
+
+    def request(i):
+        u = keyed_uniform(600, 14, np.arange(5 * i, 5 * i + 5))
+        s = min(int(u[0] * nsnap), nsnap - 1)
+        N6 = int(u[1] >= 0.5)
+        Pr = int(round(10 ** (3 + 3 * u[2])))
+        pool = pools[1 if u[3] >= 0.5 else 0]
+        off = min(int(u[4] * (pool_n - Pr)), pool_n - Pr)
+        return 2 * s + N6, pool[off: off + Pr], Pr
+
+    sv = bsi.Server(ctx, hbm_budget=args.serve_budget << 20, max_slots=args.serve_slots)
+    for fid, fl in fields.items():
+        sv.add_field(fid, fl)
+
+    def run(nreq, start, rate=None, closed=None):
+        """Submit requests start..start+nreq-1: Poisson arrivals at `rate`
+        requests/s, or closed loop with `closed` outstanding requests."""
+        tickets = []
+        rng = np.random.default_rng(start)
+        t_next = time.perf_counter()
+        for i in range(nreq):
+            j = len(tickets)
+            if j >= nbuf:                      # output buffer reuse
+                sv.wait(tickets[j - nbuf])
+            if closed is not None and j >= closed:
+                sv.wait(tickets[j - closed])
+            if rate is not None:
+                t_next += rng.exponential(1.0 / rate)
+                while time.perf_counter() < t_next:
+                    pass
+            fid, pos, Pr = request(start + i)
+            u, g = outs[j % nbuf]
+            tickets.append(sv.submit(fid, pos, u[:Pr], g[:Pr]))
+        for t in tickets:
+            sv.wait(t)
+        return sv.stats()
+
+    eprint("warm-up ...")
+    run(64, 0, closed=16)
+    sv.reset_stats()
+    eprint("closed loop (16 outstanding) ...")
+    t0 = time.perf_counter()
+    sat = run(args.serve_requests, 1000, closed=16)
+    wall = time.perf_counter() - t0
+    R = sat["completed"] / wall
+    results = {"saturated": {"requests_per_s": round(R, 1), "points_per_s": round(sat["points_per_s"], 1),
+                             "p50_ms": sat["p50_ns"] / 1e6, "p99_ms": sat["p99_ns"] / 1e6,
+                             "max_inflight": sat["max_inflight"]}}
+    eprint(f"  {R:.0f} requests/s, {sat['points_per_s']:.3e} points/s")
+    for frac in (0.5, 0.8):
+        sv.reset_stats()
+        eprint(f"open loop at {frac} x saturated rate ...")
+        st = run(args.serve_requests, 100000 * int(10 * frac), rate=frac * R)
+        results[f"rate_{frac}"] = {"rate_req_s": round(frac * R, 1), "points_per_s": round(st["points_per_s"], 1),
+                                   "p50_ms": st["p50_ns"] / 1e6, "p99_ms": st["p99_ns"] / 1e6,
+                                   "device_p50_ms": st["device_p50_ns"] / 1e6,
+                                   "device_p99_ms": st["device_p99_ns"] / 1e6,
+                                   "max_inflight": st["max_inflight"],
+                                   "peak_arena_MiB": round(st["peak_arena_bytes"] / 2**20, 1)}
+        eprint(f"  {json.dumps(results[f'rate_{frac}'])}")
+    sv.close()
+    for fl in fields.values():
+        fl.close()
+    ctx.close()
+    main_rate = results["rate_0.8"]
+    config = {"workload": f"{n_big} x {big_n}^3 + {n_small} x {small_n}^3 resident divergence-free Kolmogorov "
+                          "snapshots, FP32 grids for orders 4 and 6; Poisson requests (snapshot uniform, order "
+                          "uniform, 10^U(3,6) particles, half uniform / half clustered positions) from pinned "
+                          "host memory; value at 0.8 x the saturated request rate",
+              "resident_GiB": round(resident / 2**30, 1), "requests_per_run": args.serve_requests,
+              "slots": args.serve_slots, "hbm_budget_MiB": args.serve_budget, "parallelism": "single GPU"}
+    line = base_line(args, main_rate["points_per_s"], "points/s", 0.0, "f32", config, None, None,
+                     serving=results, p50_ms=main_rate["p50_ms"], p99_ms=main_rate["p99_ms"])
+    line["steps"] = args.serve_requests
+    line["ms_per_step"] = round(1e3 / main_rate["rate_req_s"], 4) if main_rate["rate_req_s"] else None
+    return line
+
+
+# ------------------------------------------------------------ copy form ---
 
 def copy_calibration(steps):
     """Plain device copy of a known size: the yardstick for HBM byte counters.
@@ -153,14 +626,17 @@ def copy_calibration(steps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--form", choices=("plain", "copy"), default="plain",
-                    help="plain: the interpolation workload (default); copy: 1 GiB device copy "
-                         "used to calibrate HBM byte counters")
+    ap.add_argument("--form", choices=("plain", "precision", "batch", "serve", "copy"), default="plain")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=100000)
+    ap.add_argument("--cpu-sample-precision", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort-tile", type=int, default=None)
+    ap.add_argument("--serve-scale", choices=("full", "small"), default="full")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget", type=int, default=8192, help="server arena in MiB")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -169,116 +645,13 @@ def main():
                "MI355X here; multi-GPU sharding (slabs + all-to-all transposes) is not built. "
                "Run with --gpus 1.")
         sys.exit(2)
-
     if args.form == "copy":
         print(json.dumps(copy_calibration(max(args.steps, 1))), flush=True)
         return
-
     import torch
-    import synth
-    import paper_1201_4060_amd as bsi
-    from paper_1201_4060_amd import _bsi
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    eprint("generating inputs ...")
-    uhat_np = synth.kolmogorov_spectrum(N_GRID, NCOMP, seed=FIELD_SEED)
-    pos_np = synth.uniform_positions(P, seed=POS_SEED)
-    uhat = torch.from_numpy(uhat_np).to(dev)
-    pos = torch.from_numpy(pos_np).to(dev)
-
-    ctxs = {o: bsi.Context(0) for o in ORDERS}          # one context per order: per-order stage timing
-    fields = {o: bsi.Field(ctxs[o], N_GRID, NCOMP, o, bsi.BSI_F32) for o in ORDERS}
-    outs = {o: (torch.empty((P, NCOMP), dtype=torch.float32, device=dev),
-                torch.empty((P, NCOMP, 3), dtype=torch.float32, device=dev)) for o in ORDERS}
-    cfg = None
-    if args.sort_tile is not None:
-        cfg = bsi.EvalConfig(sort_tile=args.sort_tile, block=256, xcd_remap=1)
-
-    def step():
-        for o in ORDERS:
-            fields[o].set_spectrum(uhat)
-            fields[o].eval(pos, cfg=cfg, out=outs[o])
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    for o in ORDERS:
-        _bsi.bsi_ctx_reset_timing(ctxs[o].handle)
-        _bsi.bsi_ctx_set_timing(ctxs[o].handle, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    value = len(ORDERS) * P / ((t1 - t0) / args.steps)
-
-    stages = {}
-    for o in ORDERS:
-        for st in STAGES:
-            ms, cnt = _bsi.bsi_ctx_read_timing(ctxs[o].handle, st)
-            if cnt:
-                stages[f"{st}@N{o}"] = {"avg_us": 1000.0 * ms / cnt, "launches": cnt,
-                                        "total_ms": ms}
-    for o in ORDERS:
-        _bsi.bsi_ctx_set_timing(ctxs[o].handle, False)
-    stage_ms_per_step = sum(v["total_ms"] for v in stages.values()) / args.steps
-    eprint(f"{ms_per_step:.3f} ms/step wall, {stage_ms_per_step:.3f} ms/step in library kernels")
-    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["total_ms"]):
-        eprint(f"  {k:20s} {v['avg_us']:9.1f} us x {v['launches']}")
-
-    # dominant kernel (largest share of the step among the kernels with an
-    # algorithmic byte count: gather and FFT passes) and its roofline
-    dom_key = max((k for k in stages if algorithmic_bytes(k.split("@N")[0], 4, 0) is not None),
-                  key=lambda k: stages[k]["total_ms"])
-    dom_stage, dom_order = dom_key.split("@N")
-    dom_order = int(dom_order)
-    U = distinct_stencil_points(pos_np, N_GRID, dom_order) if dom_stage == "gather" else 0
-    alg = algorithmic_bytes(dom_stage, dom_order, U)
-    avg_s = stages[dom_key]["avg_us"] * 1e-6
-    achieved = alg / avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom_key),
-                "kernel": dom_key, "algorithmic_bytes": alg, "avg_us": round(stages[dom_key]["avg_us"], 2)}
-    # the particle gather's own roofline beside it (the spec kernel)
-    gather_rl = {}
-    for o in ORDERS:
-        k = f"gather@N{o}"
-        if k in stages:
-            Uo = distinct_stencil_points(pos_np, N_GRID, o)
-            b = algorithmic_bytes("gather", o, Uo)
-            a = b / (stages[k]["avg_us"] * 1e-6) / 1e9
-            gather_rl[k] = {"achieved_GBs": round(a, 1), "frac": round(a / HBM_PEAK_GBS, 4),
-                            "algorithmic_bytes": b, "distinct_points": Uo,
-                            "avg_us": round(stages[k]["avg_us"], 2),
-                            "points_per_s": round(P / (stages[k]["avg_us"] * 1e-6), 1)}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        eprint("timing the CPU oracle on a sample ...")
-        cpu = cpu_baseline(uhat_np, pos_np, args.cpu_sample)
-
-    for o in ORDERS:
-        fields[o].close()
-        ctxs[o].close()
-
-    line = {
-        "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "256^3 x3 divergence-free Kolmogorov field, FP32 grid, orders 4 and 6, "
-                               "1e6 uniform particles; step = prefilter + eval per order",
-                   "n": N_GRID, "ncomp": NCOMP, "orders": list(ORDERS), "particles": P,
-                   "grid_dtype": "f32", "spectrum_dtype": "c128", "parallelism": "single GPU"},
-        "roofline": roofline,
-        "gather_roofline": gather_rl,
-        "stages_us": {k: round(v["avg_us"], 2) for k, v in stages.items()},
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
+    form = {"plain": form_plain, "precision": form_precision, "batch": form_batch, "serve": form_serve}
+    print(json.dumps(form[args.form](args)), flush=True)
 
 
 if __name__ == "__main__":

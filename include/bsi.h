@@ -295,6 +295,25 @@ bsi_status bsi_ctx_lookup_config(bsi_ctx* ctx, const bsi_field* field, int64_t P
 bsi_status bsi_fill_uniform_positions(bsi_ctx* ctx, uint64_t seed, int64_t P, const double* length,
                                       double* pos_dev, void* hip_stream);
 
+/* ---- synthetic workloads and memory ---------------------------------------- */
+
+/* Write a synthetic Kolmogorov-spectrum field (not part of the method; a
+ * workload generator for benchmarks and serving loads) into uhat_dev
+ * [ncomp][n][n][n/2+1], complex128 (prec = BSI_F64) or complex64 (BSI_F32):
+ * amplitude |k|^(-11/6) for 0 < |k| <= n/3 and zero elsewhere, phase 2 pi u
+ * with u from SplitMix64 (Steele, Lea and Flood 2014) output `counter` of
+ * stream c = component, the stream starting at mix((seed * 0x9E3779B97F4A7C15)
+ * xor c) and `counter` the flat half-spectrum index of the canonical member of
+ * a Hermitian pair (the other member of a k2 = 0 pair is its conjugate);
+ * divergence_free projects three components onto k-perpendicular per mode;
+ * one global factor sets the mean over components of sum_k |uhat_k|^2 over the
+ * full spectrum to 1.  n even, 2 <= n <= 4096.  Synchronises the stream. */
+bsi_status bsi_synth_kolmogorov(bsi_ctx* ctx, int32_t n, int32_t ncomp, uint64_t seed,
+                                int32_t divergence_free, int32_t prec, void* uhat_dev, void* hip_stream);
+/* Wait for the device and free the context's cached FFT and evaluation
+ * workspaces (they are allocated again on demand). */
+bsi_status bsi_ctx_trim(bsi_ctx* ctx);
+
 /* ---- stage timing -------------------------------------------------------- */
 
 /* Enable (1) or disable (0) per-stage timing on a context.  While enabled, the

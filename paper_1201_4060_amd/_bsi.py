@@ -114,6 +114,8 @@ SIGNATURES = {
     "bsi_server_stats": (ST, [VP, ctypes.POINTER(ServerReport)]),
     "bsi_server_reset_stats": (ST, [VP]),
     "bsi_server_destroy": (None, [VP]),
+    "bsi_synth_kolmogorov": (ST, [VP, I32, I32, ctypes.c_uint64, I32, I32, VP, VP]),
+    "bsi_ctx_trim": (ST, [VP]),
     "bsi_fill_uniform_positions": (ST, [VP, ctypes.c_uint64, I64, ctypes.POINTER(ctypes.c_double), VP, VP]),
 }
 
@@ -355,3 +357,16 @@ def bsi_server_reset_stats(server):
 
 def bsi_server_destroy(server):
     lib().bsi_server_destroy(server)
+
+
+def bsi_synth_kolmogorov(ctx, n, ncomp, seed, out, divergence_free=None, stream=None):
+    """out: complex128 or complex64 device tensor [ncomp][n][n][n/2+1]."""
+    if divergence_free is None:
+        divergence_free = ncomp == 3
+    prec = BSI_F64 if str(out.dtype) == "torch.complex128" else BSI_F32
+    _check(lib().bsi_synth_kolmogorov(ctx, n, ncomp, seed, 1 if divergence_free else 0, prec, _ptr(out),
+                                      stream), "bsi_synth_kolmogorov")
+
+
+def bsi_ctx_trim(ctx):
+    _check(lib().bsi_ctx_trim(ctx), "bsi_ctx_trim")
