@@ -179,12 +179,12 @@ typedef struct bsi_batch bsi_batch;
 /* Plan the evaluation of `count` items (1..65535) as one unit of work: every
  * item's particles are binned by the Morton tile of its own sort granularity,
  * and one persistent gather kernel walks a shared work list -- the non-empty
- * tiles of the items gathered from LDS tiles (4^3 or 8^3 cells) and groups of
+ * tiles of the items gathered from LDS tiles (8^3 cells) and groups of
  * 64 binned particles of the items gathered one lane per particle -- so that
  * large and small items share the GPU without a launch per item.  cfgs (count
  * entries) gives each item's configuration, or NULL for the tuned ones
- * (bsi_ctx_lookup_config); a tiled configuration whose tile the batch kernel
- * lacks uses the nearest of 4 and 8.  Results are bitwise those of
+ * (bsi_ctx_lookup_config); a tiled configuration is run with 8^3-cell tiles
+ * (one lane per particle if the class has no such tile).  Results are bitwise those of
  * bsi_eval_ex with the item's planned configuration (bsi_batch_item_config).
  * All items belong to `ctx`, share the coefficient type, and give grad for
  * all items or for none (BSI_E_INVAL otherwise).  The batch owns a device
@@ -199,7 +199,7 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
  * on every call. */
 bsi_status bsi_batch_run(bsi_batch* batch, int32_t use_graph, void* hip_stream);
 /* The configuration item `item` is evaluated with (variant 0 = tiled with
- * sort_tile 4 or 8, variant 1 = one lane per particle binned by sort_tile). */
+ * sort_tile 8, variant 1 = one lane per particle binned by sort_tile). */
 bsi_status bsi_batch_item_config(const bsi_batch* batch, int32_t item, bsi_eval_config* cfg);
 /* Device bytes of the batch workspace. */
 size_t bsi_batch_bytes(const bsi_batch* batch);

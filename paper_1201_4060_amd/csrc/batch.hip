@@ -7,8 +7,8 @@
 // Plan (host, at creation): items are laid end to end in one particle index
 // space and one bucket index space.  Each item is binned by the Morton tile of
 // its own sort granularity; the tuned (or given) configuration decides per
-// item whether its particles are gathered tile by tile from LDS (tiles of 4^3
-// or 8^3 cells) or one lane per particle from global memory.
+// item whether its particles are gathered tile by tile from LDS (tiles of 8^3
+// cells) or one lane per particle from global memory.
 //
 // Device work (one stream, no host synchronisation in between):
 //   fill        zero the bucket histogram and the two work counters
@@ -16,10 +16,10 @@
 //   scan        exclusive scan of the histogram -> binned offsets
 //   bin_scatter binned permutation and binned copy of the positions
 //   compact     list of the non-empty buckets of the tiled items
-//   gather      persistent: each workgroup (one wavefront) takes the next unit
-//               of work -- a non-empty tile of a tiled item, or 64 consecutive
-//               binned particles of a direct item -- from a global counter
-//               until none is left.
+//   gather      persistent: a grid of resident one-wavefront workgroups
+//               strides over the units of work -- the non-empty tiles of the
+//               tiled items, then groups of 64 consecutive binned particles of
+//               the direct items.
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -32,7 +32,7 @@ namespace {
 
 constexpr int BATCH_B = 64;        // threads per workgroup of the persistent gather
 constexpr int BLK = 256;           // threads per workgroup of the binning kernels
-enum : int32_t { MODE_DIRECT = 0, MODE_TILE4 = 1, MODE_TILE8 = 2 };
+enum : int32_t { MODE_DIRECT = 0, MODE_TILE8 = 2 };
 
 struct BatchItem {
     GatherArgs ga;       // hist/offs at the item's buckets; perm/pos_sorted are the batch-wide arrays
@@ -57,7 +57,7 @@ struct BatchArgs {
     uint32_t* perm;
     double* pos_sorted;
     uint2* tile_list;             // (item, bucket) of every non-empty tile
-    uint32_t* ctr;                // [0] next unit, [1] number of tile units
+    uint32_t* ctr;                // [1] number of tile units ([0] unused)
     uint32_t ndirect;
 };
 
@@ -115,53 +115,45 @@ constexpr bool batch_tile_ok() {
 }
 
 template <int N, typename CT, int C, bool GRAD>
-__device__ __forceinline__ void batch_tile(const GatherArgs& a, int mode, uint32_t bucket, u32x4* lds) {
-    if (mode == MODE_TILE8) {
-        if constexpr (batch_tile_ok<N, CT, C, 8>()) tile_eval<N, CT, C, GRAD, 8, BATCH_B>(a, bucket, lds);
-    } else {
-        if constexpr (batch_tile_ok<N, CT, C, 4>()) tile_eval<N, CT, C, GRAD, 4, BATCH_B>(a, bucket, lds);
-    }
+__device__ __forceinline__ void batch_tile(const GatherArgs& a, uint32_t bucket, u32x4* lds) {
+    // one tile shape (8^3 cells) per class keeps the kernel's register budget down
+    if constexpr (batch_tile_ok<N, CT, C, 8>()) tile_eval<N, CT, C, GRAD, 8, BATCH_B>(a, bucket, lds);
 }
 
+// Workgroup g takes units g, g + G, g + 2G, ... (G = grid size): the unit
+// index is the same in every lane, so the loop and the class dispatch are
+// scalar and every wavefront of the workgroup meets the same barriers.
 template <typename CT, bool GRAD>
 __global__ __launch_bounds__(BATCH_B) void k_batch_gather(BatchArgs b) {
     extern __shared__ u32x4 lds[];
-    const uint32_t ntile = b.ctr[1];
+    const uint32_t ntile = __builtin_amdgcn_readfirstlane(b.ctr[1]);
     const uint32_t total = ntile + b.ndirect;
-    for (;;) {
-        uint32_t u = 0;
-        if (threadIdx.x == 0) u = atomicAdd(&b.ctr[0], 1u);
-        u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, 64));
-        if (u >= total) break;
-        // everything that selects a code path is made wave-uniform explicitly,
-        // so that the class switch is a scalar branch
+    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
         if (u < ntile) {
             const uint2 e = b.tile_list[u];
             const uint32_t item = __builtin_amdgcn_readfirstlane(e.x);
             const uint32_t bucket = __builtin_amdgcn_readfirstlane(e.y);
             const BatchItem& it = b.items[item];
             const int key = __builtin_amdgcn_readfirstlane(it.N * 2 + (it.C == 3 ? 1 : 0));
-            const int mode = __builtin_amdgcn_readfirstlane(it.mode);
             switch (key) {
-                case 8: batch_tile<4, CT, 1, GRAD>(it.ga, mode, bucket, lds); break;
-                case 9: batch_tile<4, CT, 3, GRAD>(it.ga, mode, bucket, lds); break;
-                case 12: batch_tile<6, CT, 1, GRAD>(it.ga, mode, bucket, lds); break;
-                default: batch_tile<6, CT, 3, GRAD>(it.ga, mode, bucket, lds); break;
+                case 8: batch_tile<4, CT, 1, GRAD>(it.ga, bucket, lds); break;
+                case 9: batch_tile<4, CT, 3, GRAD>(it.ga, bucket, lds); break;
+                case 12: batch_tile<6, CT, 1, GRAD>(it.ga, bucket, lds); break;
+                default: batch_tile<6, CT, 3, GRAD>(it.ga, bucket, lds); break;
             }
         } else {
             const uint32_t d = u - ntile;
             const uint32_t item = __builtin_amdgcn_readfirstlane(uint32_t(b.dunit_item[d]));
             const BatchItem& it = b.items[item];
+            const int key = __builtin_amdgcn_readfirstlane(it.N * 2 + (it.C == 3 ? 1 : 0));
             const long r = long(d - it.ubase) * BATCH_B + threadIdx.x;
-            if (r < it.ga.P) {
-                const long j = long(it.pbase) + r;
-                const int key = __builtin_amdgcn_readfirstlane(it.N * 2 + (it.C == 3 ? 1 : 0));
-                switch (key) {
-                    case 8: direct_eval<4, CT, 1, GRAD>(it.ga, j); break;
-                    case 9: direct_eval<4, CT, 3, GRAD>(it.ga, j); break;
-                    case 12: direct_eval<6, CT, 1, GRAD>(it.ga, j); break;
-                    default: direct_eval<6, CT, 3, GRAD>(it.ga, j); break;
-                }
+            const long P = it.ga.P;
+            const long j = long(it.pbase) + (r < P ? r : P - 1);  // lanes past the end repeat the last
+            switch (key) {
+                case 8: direct_eval<4, CT, 1, GRAD>(it.ga, j, r < P); break;
+                case 9: direct_eval<4, CT, 3, GRAD>(it.ga, j, r < P); break;
+                case 12: direct_eval<6, CT, 1, GRAD>(it.ga, j, r < P); break;
+                default: direct_eval<6, CT, 3, GRAD>(it.ga, j, r < P); break;
             }
         }
     }
@@ -263,21 +255,16 @@ struct bsi_batch {
 namespace bsi {
 
 // Plan choice of one item from a configuration: a tiled configuration keeps
-// the tiled gather with the batch kernel's tile nearest to its sort tile (4 up
-// to 6 cells, else 8; the other one if that one does not fit); anything else
-// is gathered one lane per particle, binned with the configuration's tile.
+// the tiled gather, with the batch kernel's 8^3-cell tiles when the class has
+// them; anything else is gathered one lane per particle, binned with the
+// configuration's tile.
 static void item_mode(const bsi_field* f, const bsi_eval_config& c, int* mode, int* tile) {
     const int nmax = std::max(f->n[0], std::max(f->n[1], f->n[2]));
     const int tmin = (nmax + 255) / 256;  // at most 2^24 buckets
-    if (c.variant == 0 && c.sort_tile > 0) {
-        const int first = c.sort_tile <= 6 ? 4 : 8;
-        for (int T : {first, 12 - first}) {
-            if (T >= tmin && batch_tile_supported(f->desc.coef, f->N, f->C, T)) {
-                *mode = T == 4 ? MODE_TILE4 : MODE_TILE8;
-                *tile = T;
-                return;
-            }
-        }
+    if (c.variant == 0 && c.sort_tile > 0 && 8 >= tmin && batch_tile_supported(f->desc.coef, f->N, f->C, 8)) {
+        *mode = MODE_TILE8;
+        *tile = 8;
+        return;
     }
     *mode = MODE_DIRECT;
     *tile = std::max(c.sort_tile > 0 ? c.sort_tile : 8, tmin);

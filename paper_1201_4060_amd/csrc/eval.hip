@@ -80,7 +80,10 @@ __global__ __launch_bounds__(B) void k_gather_tiled(GatherArgs a) {
     const uint32_t nbt = a.nbuckets_finite + 1;
     const uint32_t b0 = uint32_t(logical_block(a.xcd_remap)) * a.tiles_per_group;
     const uint32_t b1 = min(b0 + a.tiles_per_group, nbt);
-    for (uint32_t cur = next_tile(a, b0, b1); cur < b1; cur = next_tile(a, cur + 1, b1))
+    // the tile index is made wave-uniform so that the loop (which holds
+    // workgroup barriers) is scalar
+    for (uint32_t cur = __builtin_amdgcn_readfirstlane(next_tile(a, b0, b1)); cur < b1;
+         cur = __builtin_amdgcn_readfirstlane(next_tile(a, cur + 1, b1)))
         tile_eval<N, CT, C, GRAD, T, B>(a, cur, tile_v);
 }
 

@@ -434,26 +434,35 @@ struct TileLoad {
 // One particle evaluated straight from the grid in global memory (the caches
 // provide the reuse between neighbouring binned particles).  j is the
 // particle's slot in binned order, or its index when the particles are not
-// binned; positions come from the binned copy when there is one.
+// binned; positions come from the binned copy when there is one.  With store
+// false the lane computes but writes nothing (a lane past the end of a group).
 template <int N, typename CT, int C, bool GRAD>
-__device__ __forceinline__ void direct_eval(const GatherArgs& a, long j) {
+__device__ __forceinline__ void direct_eval(const GatherArgs& a, long j, bool store = true) {
     using AT = typename Acc<CT>::type;
     const long p = a.perm ? long(a.perm[j]) : j;
     const double* xp = a.pos_sorted ? a.pos_sorted + 3 * j : a.pos + 3 * p;
     const double x[3] = {xp[0], xp[1], xp[2]};
     int cell[3];
     AT w[3][N], wd[3][N];
+    // if/else rather than an early return: the function is inlined into loops
+    // that hold workgroup barriers
     if (!particle_setup_x<N, AT>(a, x, cell, w, wd)) {
-        write_nan<AT, C, GRAD>(a, p);
-        atomicAdd(a.nonfinite, 1ull);
-        return;
+        if (store) {
+            write_nan<AT, C, GRAD>(a, p);
+            atomicAdd(a.nonfinite, 1ull);
+        }
+    } else {
+        const CT* base = static_cast<const CT*>(a.grid) + (long(cell[0]) * a.P1 + cell[1]) * a.pitch2 +
+                         long(cell[2]) * C;
+        const long rowA = long(a.P1) * a.pitch2;
+        const long rowB = a.pitch2;
+        Partial<AT, C> lo, hi;
+        auto row = [&](int ia, int ib) { return base + ia * rowA + ib * rowB; };
+        contract_planes<N, CT, AT, C, GRAD, N / 2>(w[0], wd[0], w, wd, row, lo);
+        contract_planes<N, CT, AT, C, GRAD, N / 2>(w[0] + N / 2, wd[0] + N / 2, w, wd,
+                                                   [&](int k, int ib) { return row(N / 2 + k, ib); }, hi);
+        if (store) store_sum<AT, C, GRAD>(a, p, lo, hi);
     }
-    const CT* base = static_cast<const CT*>(a.grid) + (long(cell[0]) * a.P1 + cell[1]) * a.pitch2 +
-                     long(cell[2]) * C;
-    const long rowA = long(a.P1) * a.pitch2;
-    const long rowB = a.pitch2;
-    contract_and_store<N, CT, AT, C, GRAD>(a, p, w, wd,
-                                           [&](int ia, int ib) { return base + ia * rowA + ib * rowB; });
 }
 
 // LDS bytes one workgroup of B threads needs for tiles of T^3 cells.
@@ -462,29 +471,15 @@ constexpr int tile_lds_bytes() {
     return (TileGeom<N, CT, C, T>::SLOTS + B - 1) / B * B * 16;
 }
 
-// All particles of Morton tile `cur` (T^3 cells) evaluated by one workgroup of
-// B threads from an LDS copy of the tile's (T+N-1)^3 block of the grid.  All
-// 16-byte loads of the block are issued at once (one memory round trip)
-// straight into `tile_v` (tile_lds_bytes() of LDS); the tile's binned
-// positions are contiguous.  Two lanes per particle (one half of the axis-0 sum each,
-// combined with a lane shuffle) while the tile holds at most B/2 particles,
-// one lane per particle otherwise.  `cur` == nbuckets_finite is the bucket of
-// particles without a cell: they get NaN outputs and are counted.  Every
-// thread of the workgroup must call this with the same `cur`.
+// The cells of tile `cur` (count particles from binned slot start): see tile_eval.
 template <int N, typename CT, int C, bool GRAD, int T, int B>
-__device__ __forceinline__ void tile_eval(const GatherArgs& a, uint32_t cur, u32x4* tile_v) {
+__device__ __forceinline__ void tile_eval_cells(const GatherArgs& a, uint32_t cur, uint32_t count, uint32_t start,
+                                                u32x4* tile_v) {
     using AT = typename Acc<CT>::type;
     using G = TileGeom<N, CT, C, T>;
     constexpr int PERB = (G::SLOTS + B - 1) / B;
     const CT* tile = reinterpret_cast<const CT*>(tile_v);
     const int tid = threadIdx.x;
-    const uint32_t count = a.hist[cur];
-    const uint32_t start = a.offs[cur];
-    if (cur == a.nbuckets_finite) {
-        for (uint32_t j = tid; j < count; j += B) write_nan<AT, C, GRAD>(a, long(a.perm[start + j]));
-        if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
-        return;
-    }
     const int o0 = int(compact3(cur >> 2)) * T;
     const int o1 = int(compact3(cur >> 1)) * T;
     const int o2 = int(compact3(cur)) * T;
@@ -560,6 +555,31 @@ __device__ __forceinline__ void tile_eval(const GatherArgs& a, uint32_t cur, u32
         }
     }
     lds_barrier();
+}
+
+// All particles of Morton tile `cur` (T^3 cells) evaluated by one workgroup of
+// B threads from an LDS copy of the tile's (T+N-1)^3 block of the grid.  All
+// 16-byte loads of the block are issued at once (one memory round trip)
+// straight into `tile_v` (tile_lds_bytes() of LDS); the tile's binned
+// positions are contiguous.  Two lanes per particle (one half of the axis-0 sum each,
+// combined with a lane shuffle) while the tile holds at most B/2 particles,
+// one lane per particle otherwise.  `cur` == nbuckets_finite is the bucket of
+// particles without a cell: they get NaN outputs and are counted.  Every
+// thread of the workgroup must call this with the same `cur`.
+template <int N, typename CT, int C, bool GRAD, int T, int B>
+__device__ __forceinline__ void tile_eval(const GatherArgs& a, uint32_t cur, u32x4* tile_v) {
+    using AT = typename Acc<CT>::type;
+    const int tid = threadIdx.x;
+    // every value that steers a loop or branch holding a barrier is made
+    // wave-uniform explicitly, so that those loops are scalar
+    const uint32_t count = __builtin_amdgcn_readfirstlane(a.hist[cur]);
+    const uint32_t start = __builtin_amdgcn_readfirstlane(a.offs[cur]);
+    if (cur == a.nbuckets_finite) {
+        for (uint32_t j = tid; j < count; j += B) write_nan<AT, C, GRAD>(a, long(a.perm[start + j]));
+        if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
+    } else {
+        tile_eval_cells<N, CT, C, GRAD, T, B>(a, cur, count, start, tile_v);
+    }
 }
 
 }  // namespace bsi
