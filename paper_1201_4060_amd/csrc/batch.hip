@@ -11,10 +11,10 @@
 // cells) or one lane per particle from global memory.
 //
 // Device work (one stream, no host synchronisation in between):
-//   fill        zero the bucket histogram and the two work counters
-//   bin_count   cell and Morton bucket of every particle (all items at once)
-//   scan        exclusive scan of the histogram -> binned offsets
-//   bin_scatter binned permutation and binned copy of the positions
+//   fill        zero the work counters
+//   grouping    cell and Morton bucket of every particle (all items at once),
+//               grouped by bucket without global atomics (gather.hpp): bucket
+//               table, binned permutation and binned copy of the positions
 //   compact     list of the non-empty buckets of the tiled items
 //   gather      persistent: a grid of resident one-wavefront workgroups
 //               strides over the units of work -- the non-empty tiles of the
@@ -43,6 +43,8 @@ struct BatchItem {
     uint32_t pblk;       // first binning workgroup of the item
     uint32_t bblk;       // first compaction workgroup of the item (tiled items)
     uint32_t ubase;      // first direct unit of the item (direct items)
+    uint32_t cbase;      // first coarse grouping range of the item
+    int32_t cshift;      // item bucket b lies in coarse range cbase + (b >> cshift)
 };
 
 struct BatchArgs {
@@ -52,10 +54,9 @@ struct BatchArgs {
     const uint16_t* dunit_item;   // item of each direct unit
     uint32_t* hist;
     uint32_t* offs;
-    uint32_t* key;
-    uint32_t* rank;
     uint32_t* perm;
     double* pos_sorted;
+    const uint32_t* cstart;       // first bucket of every coarse grouping range (+ end)
     uint2* tile_list;             // (item, bucket) of every non-empty tile
     uint32_t* ctr;                // [1] number of tile units ([0] unused)
     uint32_t ndirect;
@@ -76,29 +77,51 @@ __device__ __forceinline__ uint32_t item_bucket(const BatchItem& it, const doubl
            spread3(uint32_t(c[2]) / T);
 }
 
-__global__ __launch_bounds__(BLK) void k_batch_bin_count(BatchArgs b) {
-    const BatchItem& it = b.items[b.pblock_item[blockIdx.x]];
-    const long p = long(blockIdx.x - it.pblk) * BLK + threadIdx.x;
-    if (p >= it.ga.P) return;
-    const double x[3] = {it.ga.pos[3 * p], it.ga.pos[3 * p + 1], it.ga.pos[3 * p + 2]};
-    const uint32_t k = it.bbase + item_bucket(it, x);
-    const long g = long(it.pbase) + p;
-    b.key[g] = k;
-    b.rank[g] = atomicAdd(&b.hist[k], 1u);
-}
+// Grouping slots of a batch: item i owns the slots [pblk * BLK, (pblk +
+// ceil(P / BLK)) * BLK), slot pblk * BLK + p holding its particle p; the
+// slots past P are padding.
+struct BatchSlots {
+    const BatchItem* items;
+    const uint16_t* pblock_item;
+    __device__ __forceinline__ const BatchItem& item_of(long i, long& p) const {
+        const BatchItem& it = items[pblock_item[i / BLK]];
+        p = i - long(it.pblk) * BLK;
+        return it;
+    }
+    __device__ __forceinline__ bool key(long i, uint32_t& k, uint32_t& c) const {
+        long p;
+        const BatchItem& it = item_of(i, p);
+        if (p >= it.ga.P) return false;
+        const double x[3] = {it.ga.pos[3 * p], it.ga.pos[3 * p + 1], it.ga.pos[3 * p + 2]};
+        const uint32_t lk = item_bucket(it, x);
+        k = it.bbase + lk;
+        c = it.cbase + (lk >> it.cshift);
+        return true;
+    }
+    __device__ __forceinline__ uint32_t coarse(long i, uint32_t k) const {
+        long p;
+        const BatchItem& it = item_of(i, p);
+        return it.cbase + ((k - it.bbase) >> it.cshift);
+    }
+    __device__ __forceinline__ void fetch(uint32_t i, uint32_t& local, double* x) const {
+        long p;
+        const BatchItem& it = item_of(i, p);
+        local = uint32_t(p);
+        x[0] = it.ga.pos[3 * p];
+        x[1] = it.ga.pos[3 * p + 1];
+        x[2] = it.ga.pos[3 * p + 2];
+    }
+};
 
-__global__ __launch_bounds__(BLK) void k_batch_bin_scatter(BatchArgs b) {
-    const BatchItem& it = b.items[b.pblock_item[blockIdx.x]];
-    const long p = long(blockIdx.x - it.pblk) * BLK + threadIdx.x;
-    if (p >= it.ga.P) return;
-    const long g = long(it.pbase) + p;
-    const uint32_t dst = b.offs[b.key[g]] + b.rank[g];
-    b.perm[dst] = uint32_t(p);
-    const double x0 = it.ga.pos[3 * p], x1 = it.ga.pos[3 * p + 1], x2 = it.ga.pos[3 * p + 2];
-    b.pos_sorted[3 * long(dst)] = x0;
-    b.pos_sorted[3 * long(dst) + 1] = x1;
-    b.pos_sorted[3 * long(dst) + 2] = x2;
-}
+// Coarse ranges of a batch: range c holds the batch buckets [cstart[c],
+// cstart[c + 1]).
+struct TableCoarse {
+    const uint32_t* cstart;
+    __device__ __forceinline__ void range(uint32_t c, uint32_t& lo, uint32_t& hi) const {
+        lo = cstart[c];
+        hi = cstart[c + 1];
+    }
+};
 
 __global__ __launch_bounds__(BLK) void k_batch_compact(BatchArgs b) {
     const uint32_t item = b.bblock_item[blockIdx.x];
@@ -241,7 +264,8 @@ struct bsi_batch {
     int nitems = 0;                      // items with P > 0
     uint64_t Ptot = 0, Btot = 0;
     uint32_t npblocks = 0, nbblocks = 0, ndirect = 0;
-    size_t nsums = 0;
+    GrpPlan grp;                         // grouping of the particle slots by bucket
+    GrpBuffers gbuf{};
     void* ws = nullptr;
     size_t ws_bytes = 0;
     BatchArgs args{};
@@ -276,18 +300,13 @@ static bsi_status enqueue(bsi_batch* b, hipStream_t s) {
     bsi_ctx* ctx = b->ctx;
     if (b->nitems == 0) return BSI_OK;
     const BatchArgs& a = b->args;
-    const unsigned fillb = unsigned(std::min<uint64_t>((b->Btot + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_fill_u32, dim3(fillb), dim3(256), 0, s, a.hist, long(b->Btot), 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, a.ctr, 2L, 0u);
     {
         StageTimer tm(ctx, "batch_bin", s);
-        hipLaunchKernelGGL(k_batch_bin_count, dim3(b->npblocks), dim3(BLK), 0, s, a);
-        hipLaunchKernelGGL(k_scan_sums, dim3(unsigned(b->nsums)), dim3(SCAN_BLOCK), 0, s, a.hist, long(b->Btot),
-                           a.offs + b->Btot);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, a.offs + b->Btot, int(b->nsums));
-        hipLaunchKernelGGL(k_scan_apply, dim3(unsigned(b->nsums)), dim3(SCAN_BLOCK), 0, s, a.hist, long(b->Btot),
-                           a.offs + b->Btot, a.offs);
-        hipLaunchKernelGGL(k_batch_bin_scatter, dim3(b->npblocks), dim3(BLK), 0, s, a);
+        const BatchSlots slots{a.items, a.pblock_item};
+        grp_count(slots, b->grp, b->gbuf, s);
+        grp_scan(b->grp, b->gbuf, s);
+        grp_scatter(slots, TableCoarse{a.cstart}, slots, b->grp, b->gbuf, a.hist, a.offs, a.perm, a.pos_sorted, s);
         if (b->nbblocks) hipLaunchKernelGGL(k_batch_compact, dim3(b->nbblocks), dim3(BLK), 0, s, a);
     }
     {
@@ -412,25 +431,48 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
         pbase += uint64_t(it.P);
         Btot += nbf + 1;
     }
+    // coarse grouping ranges: per item about `target` particles each; the
+    // target doubles until all of them fit the grouping's LDS table
+    std::vector<uint32_t> cstart;
+    for (uint64_t target = GRP_TARGET;; target *= 2) {
+        uint64_t nc = 0;
+        for (auto& x : hi) {
+            x.cshift = grp_shift(x.nb, long(x.ga.P), target);
+            x.cbase = uint32_t(nc);
+            nc += (uint64_t(x.nb) + (uint64_t(1) << x.cshift) - 1) >> x.cshift;
+        }
+        if (nc <= GRP_COARSE_MAX) break;
+        if (target > (uint64_t(1) << 40)) {
+            delete b;
+            set_error("too many buckets in one batch; use coarser sort tiles");
+            return BSI_E_INVAL;
+        }
+    }
+    uint32_t fine_max = 1;
+    for (const auto& x : hi) {
+        for (uint64_t lo = 0; lo < x.nb; lo += uint64_t(1) << x.cshift) cstart.push_back(uint32_t(x.bbase + lo));
+        fine_max = std::max(fine_max, std::min<uint32_t>(x.nb, uint32_t(1) << x.cshift));
+    }
+    cstart.push_back(uint32_t(Btot));
     if (Btot >= (uint64_t(1) << 32)) {
         delete b;
         set_error("too many buckets in one batch; use coarser sort tiles");
         return BSI_E_INVAL;
     }
+    b->grp = grp_plan(long(pblock.size()) * BLK, uint32_t(pbase), uint32_t(cstart.size() - 1), fine_max);
     b->nitems = int(hi.size());
     b->Ptot = pbase;
     b->Btot = Btot;
     b->npblocks = uint32_t(pblock.size());
     b->nbblocks = uint32_t(bblock.size());
     b->ndirect = uint32_t(dunit.size());
-    b->nsums = (Btot + SCAN_CHUNK - 1) / SCAN_CHUNK;
     b->lds = size_t(lds);
     if (b->nitems == 0) {
         *out = b;
         return BSI_OK;
     }
-    // workspace: tables, histogram + offsets (+ scan sums), keys, ranks, perm,
-    // binned positions, tile list, counters
+    // workspace: tables, bucket table (counts, offsets), grouping scratch,
+    // perm, binned positions, tile list, counters
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -442,9 +484,9 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     const size_t o_bblock = take(std::max<size_t>(bblock.size(), 1) * sizeof(uint16_t));
     const size_t o_dunit = take(std::max<size_t>(dunit.size(), 1) * sizeof(uint16_t));
     const size_t o_hist = take(Btot * sizeof(uint32_t));
-    const size_t o_offs = take((Btot + b->nsums) * sizeof(uint32_t));
-    const size_t o_key = take(pbase * sizeof(uint32_t));
-    const size_t o_rank = take(pbase * sizeof(uint32_t));
+    const size_t o_offs = take(Btot * sizeof(uint32_t));
+    const size_t o_grp = take(grp_scratch_words(b->grp) * sizeof(uint32_t));
+    const size_t o_cstart = take(cstart.size() * sizeof(uint32_t));
     const size_t o_perm = take(pbase * sizeof(uint32_t));
     const size_t o_pos = take(3 * pbase * sizeof(double));
     const size_t o_list = take(std::max<uint64_t>(Btot, 1) * sizeof(uint2));
@@ -464,8 +506,8 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     a.dunit_item = reinterpret_cast<const uint16_t*>(base + o_dunit);
     a.hist = reinterpret_cast<uint32_t*>(base + o_hist);
     a.offs = reinterpret_cast<uint32_t*>(base + o_offs);
-    a.key = reinterpret_cast<uint32_t*>(base + o_key);
-    a.rank = reinterpret_cast<uint32_t*>(base + o_rank);
+    b->gbuf = grp_buffers(b->grp, reinterpret_cast<uint32_t*>(base + o_grp));
+    a.cstart = reinterpret_cast<const uint32_t*>(base + o_cstart);
     a.perm = reinterpret_cast<uint32_t*>(base + o_perm);
     a.pos_sorted = reinterpret_cast<double*>(base + o_pos);
     a.tile_list = reinterpret_cast<uint2*>(base + o_list);
@@ -489,6 +531,7 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     up(o_pblock, pblock.data(), pblock.size() * sizeof(uint16_t));
     up(o_bblock, bblock.data(), bblock.size() * sizeof(uint16_t));
     up(o_dunit, dunit.data(), dunit.size() * sizeof(uint16_t));
+    up(o_cstart, cstart.data(), cstart.size() * sizeof(uint32_t));
     // persistent grid: as many one-wavefront workgroups as stay resident
     int per_cu = 0;
     if (st == BSI_OK && hipOccupancyMaxActiveBlocksPerMultiprocessor(

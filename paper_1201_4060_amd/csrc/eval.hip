@@ -25,42 +25,41 @@ __global__ void k_debug_cells(CellArgs a, int32_t* cell, double* t) {
 
 // ---------------------------------------------------------------- binning ---
 
-__global__ void k_bin_count(CellArgs a, int tile, uint32_t nbuckets_finite, uint32_t* __restrict__ hist,
-                            uint32_t* __restrict__ key, uint32_t* __restrict__ rank) {
-    const long p = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (p >= a.P) return;
-    const int n[3] = {a.n0, a.n1, a.n2};
-    const double ih[3] = {a.ih0, a.ih1, a.ih2};
-    int c[3];
-    double tt[3];
-    bool ok = true;
+// Key of a particle: the Morton index of its sort tile, or nbuckets_finite
+// for a non-finite position; its coarse range is key >> shift.
+struct MortonKey {
+    CellArgs a;
+    int tile;
+    uint32_t nbuckets_finite;
+    int shift;
+    __device__ __forceinline__ uint32_t coarse(long, uint32_t k) const { return k >> shift; }
+    __device__ __forceinline__ bool key(long p, uint32_t& k, uint32_t& cr) const {
+        const int n[3] = {a.n0, a.n1, a.n2};
+        const double ih[3] = {a.ih0, a.ih1, a.ih2};
+        int c[3];
+        double tt[3];
+        bool ok = true;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) ok = cell_of(a.pos[3 * p + d], ih[d], n[d], c[d], tt[d]) && ok;
-    uint32_t k = nbuckets_finite;  // overflow bucket for non-finite particles
-    if (ok)
-        k = (spread3(uint32_t(c[0] / tile)) << 2) | (spread3(uint32_t(c[1] / tile)) << 1) |
-            spread3(uint32_t(c[2] / tile));
-    key[p] = k;
-    rank[p] = atomicAdd(&hist[k], 1u);
-}
-
-// perm[dst] = p and, when pos_sorted is given, a copy of the particle's
-// position at its binned slot (so that the gather reads binned positions
-// contiguously instead of through perm).
-__global__ void k_bin_scatter(long P, const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
-                              const uint32_t* __restrict__ offs, uint32_t* __restrict__ perm,
-                              const double* __restrict__ pos, double* __restrict__ pos_sorted) {
-    const long p = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (p >= P) return;
-    const uint32_t dst = offs[key[p]] + rank[p];
-    perm[dst] = uint32_t(p);
-    if (pos_sorted) {
-        const double x0 = pos[3 * p], x1 = pos[3 * p + 1], x2 = pos[3 * p + 2];
-        pos_sorted[3 * long(dst)] = x0;
-        pos_sorted[3 * long(dst) + 1] = x1;
-        pos_sorted[3 * long(dst) + 2] = x2;
+        for (int d = 0; d < 3; ++d) ok = cell_of(a.pos[3 * p + d], ih[d], n[d], c[d], tt[d]) && ok;
+        k = nbuckets_finite;
+        if (ok)
+            k = (spread3(uint32_t(c[0] / tile)) << 2) | (spread3(uint32_t(c[1] / tile)) << 1) |
+                spread3(uint32_t(c[2] / tile));
+        cr = k >> shift;
+        return true;
     }
-}
+};
+
+// Positions of one particle array, slot i = particle i.
+struct ArrayPositions {
+    const double* pos;
+    __device__ __forceinline__ void fetch(uint32_t i, uint32_t& local, double* x) const {
+        local = i;
+        x[0] = pos[3 * long(i)];
+        x[1] = pos[3 * long(i) + 1];
+        x[2] = pos[3 * long(i) + 2];
+    }
+};
 
 // ----------------------------------------------------------------- gather ---
 
@@ -201,36 +200,37 @@ size_t bin_bucket_count(const bsi_field* f, int tile) {
     return size_t(1) << (3 * bits);
 }
 
-// Bucket arrays live at the start of the binning scratch: hist[nb], offs[nb], ...
+// Bucket arrays live at the start of the binning scratch: hist[nb], offs[nb],
+// then the grouping scratch.  At most 2^24 + 1 keys (effective_tile).
+static GrpPlan bin_plan(const bsi_field* f, long P, int tile, int* shift) {
+    const uint64_t nb = bin_bucket_count(f, tile) + 1;
+    *shift = grp_shift(nb, P);
+    const uint32_t ncoarse = uint32_t((nb + (uint64_t(1) << *shift) - 1) >> *shift);
+    return grp_plan(P, uint32_t(P), ncoarse, uint32_t(1) << *shift);
+}
+
 bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, uint32_t* perm, void* scratch,
                    double* pos_sorted, hipStream_t s) {
     const size_t nbf = bin_bucket_count(f, tile);
     const size_t nb = nbf + 1;
+    int shift = 0;
+    const GrpPlan g = bin_plan(f, P, tile, &shift);
     uint32_t* hist = static_cast<uint32_t*>(scratch);
     uint32_t* offs = hist + nb;
-    const size_t nsums = (nb + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    uint32_t* sums = offs + nb;
-    uint32_t* key = sums + nsums;
-    uint32_t* rank = key + P;
-    const unsigned fillb = unsigned(std::min<size_t>((nb + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_fill_u32, dim3(fillb), dim3(256), 0, s, hist, long(nb), 0u);
-    const CellArgs ca = cell_args(f, pos, P);
-    const unsigned pb = unsigned((P + 255) / 256);
+    const GrpBuffers gb = grp_buffers(g, offs + nb);
+    const MortonKey mk{cell_args(f, pos, P), tile, uint32_t(nbf), shift};
     {
         StageTimer tm(f->ctx, "bin_count", s);
-        hipLaunchKernelGGL(k_bin_count, dim3(pb), dim3(256), 0, s, ca, tile, uint32_t(nbf), hist, key, rank);
+        grp_count(mk, g, gb, s);
     }
     {
         StageTimer tm(f->ctx, "bin_scan", s);
-        hipLaunchKernelGGL(k_scan_sums, dim3(unsigned(nsums)), dim3(SCAN_BLOCK), 0, s, hist, long(nb), sums);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, sums, int(nsums));
-        hipLaunchKernelGGL(k_scan_apply, dim3(unsigned(nsums)), dim3(SCAN_BLOCK), 0, s, hist, long(nb), sums,
-                           offs);
+        grp_scan(g, gb, s);
     }
     {
         StageTimer tm(f->ctx, "bin_scatter", s);
-        hipLaunchKernelGGL(k_bin_scatter, dim3(pb), dim3(256), 0, s, P, key, rank, offs, perm, pos,
-                           pos_sorted);
+        grp_scatter(mk, ShiftCoarse{shift, uint32_t(nb)}, ArrayPositions{pos}, g, gb, hist, offs, perm, pos_sorted,
+                    s);
     }
     BSI_HIP(hipGetLastError());
     return BSI_OK;
@@ -238,8 +238,8 @@ bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, uint32_t* 
 
 size_t bin_scratch_bytes(const bsi_field* f, long P, int tile) {
     const size_t nb = bin_bucket_count(f, tile) + 1;
-    const size_t nsums = (nb + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    return (2 * nb + nsums + 2 * size_t(P)) * sizeof(uint32_t);
+    int shift = 0;
+    return (2 * nb + grp_scratch_words(bin_plan(f, P, tile, &shift))) * sizeof(uint32_t);
 }
 
 bool tiled_supported(const bsi_field* f, int tile) {

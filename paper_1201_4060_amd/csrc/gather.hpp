@@ -148,6 +148,253 @@ static __global__ void k_fill_u32(uint32_t* p, long n, uint32_t v) {
         p[i] = v;
 }
 
+// ------------------------------------------------------- grouping by key ---
+// Particles are grouped by bucket key with a two-level counting sort that uses
+// no global atomics (their throughput, not the data volume, bounds a one-pass
+// counting sort with one atomic per particle).  The keys [0, nbuckets) are
+// split into `ncoarse` contiguous coarse ranges of at most GRP_FINE_MAX keys,
+// sized by the caller so that each holds a few hundred particles:
+//   k_grp_hist    each block of `ipt * GRP_BLOCK` grouping slots computes the
+//                 keys, stores them, and counts its slots per coarse range in
+//                 LDS; the counts are stored range-major
+//   (scan)        exclusive scan of the counts: where each block's particles
+//                 of each coarse range go
+//   k_grp_coarse  each block scatters (key, slot) into the coarse ranges
+//   k_grp_fine    one workgroup per coarse range: LDS histogram of its keys,
+//                 the bucket table (count and first binned slot of every key
+//                 of the range, empty keys included, so the table needs no
+//                 clearing) and the final scatter of the permutation and the
+//                 binned positions.
+// The order inside a bucket is whatever the LDS atomics give; no result
+// depends on it.  Blocks of the two coarse passes are mapped so that each XCD
+// takes one contiguous range of slots, which keeps the partial-line writes of
+// one coarse range in one L2.
+//
+// KeySrc::key(i, &k, &c) gives the key and coarse range of grouping slot i,
+// or false for a slot that holds no particle (padding); KeySrc::coarse(i, k)
+// gives the coarse range of slot i's key k again.  Coarse::range(c, &lo, &hi)
+// gives the keys [lo, hi) of range c.  Src::fetch(i, &local, x) gives the
+// particle of slot i: its index in its own position array and its position.
+
+constexpr int GRP_BLOCK = SCAN_BLOCK;
+constexpr uint32_t GRP_FINE_MAX = 8192;      // keys per coarse range: 32 KB of LDS
+constexpr uint32_t GRP_COARSE_MAX = 8192;    // coarse ranges: 32 KB of LDS
+constexpr uint32_t GRP_NONE = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t grp_block(long nblk) {
+    const long b = blockIdx.x;
+    const long q = nblk / 8, r = nblk % 8;
+    const long x = b % 8, i = b / 8;
+    return uint32_t(x * q + (x < r ? x : r) + i);
+}
+
+template <typename KeySrc>
+static __global__ __launch_bounds__(GRP_BLOCK) void k_grp_hist(KeySrc ks, long nidx, int ipt, uint32_t ncoarse,
+                                                              long nblk, uint32_t* __restrict__ key,
+                                                              uint32_t* __restrict__ counts) {
+    extern __shared__ uint32_t lh[];
+    for (uint32_t c = threadIdx.x; c < ncoarse; c += GRP_BLOCK) lh[c] = 0;
+    __syncthreads();
+    const uint32_t blk = grp_block(nblk);
+    const long b0 = long(blk) * ipt * GRP_BLOCK;
+    for (int q = 0; q < ipt; ++q) {
+        const long i = b0 + long(q) * GRP_BLOCK + threadIdx.x;
+        if (i < nidx) {
+            uint32_t k, c;
+            if (ks.key(i, k, c)) {
+                key[i] = k;
+                atomicAdd(&lh[c], 1u);
+            } else {
+                key[i] = GRP_NONE;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t c = threadIdx.x; c < ncoarse; c += GRP_BLOCK) counts[long(c) * nblk + blk] = lh[c];
+}
+
+template <typename KeySrc>
+static __global__ __launch_bounds__(GRP_BLOCK) void k_grp_coarse(KeySrc ks, const uint32_t* __restrict__ key,
+                                                                long nidx, int ipt, uint32_t ncoarse, long nblk,
+                                                                const uint32_t* __restrict__ gscan,
+                                                                uint32_t* __restrict__ tkey,
+                                                                uint32_t* __restrict__ tval) {
+    extern __shared__ uint32_t cur[];
+    const uint32_t blk = grp_block(nblk);
+    for (uint32_t c = threadIdx.x; c < ncoarse; c += GRP_BLOCK) cur[c] = gscan[long(c) * nblk + blk];
+    __syncthreads();
+    const long b0 = long(blk) * ipt * GRP_BLOCK;
+    for (int q = 0; q < ipt; ++q) {
+        const long i = b0 + long(q) * GRP_BLOCK + threadIdx.x;
+        if (i < nidx) {
+            const uint32_t k = key[i];
+            if (k != GRP_NONE) {
+                const uint32_t d = atomicAdd(&cur[ks.coarse(i, k)], 1u);
+                tkey[d] = k;
+                tval[d] = uint32_t(i);
+            }
+        }
+    }
+}
+
+template <typename Coarse, typename Src>
+static __global__ __launch_bounds__(GRP_BLOCK) void k_grp_fine(Coarse cm, Src src, const uint32_t* __restrict__ tkey,
+                                                              const uint32_t* __restrict__ tval, uint32_t nvalid,
+                                                              uint32_t ncoarse, long nblk,
+                                                              const uint32_t* __restrict__ gscan,
+                                                              uint32_t* __restrict__ hist,
+                                                              uint32_t* __restrict__ offs,
+                                                              uint32_t* __restrict__ perm,
+                                                              double* __restrict__ pos_sorted) {
+    extern __shared__ uint32_t lh[];
+    __shared__ uint32_t sh[GRP_BLOCK];
+    const int tid = threadIdx.x;
+    const uint32_t c = blockIdx.x;
+    const uint32_t start = gscan[long(c) * nblk];
+    const uint32_t end = c + 1 < ncoarse ? gscan[long(c + 1) * nblk] : nvalid;
+    uint32_t klo, khi;
+    cm.range(c, klo, khi);
+    const uint32_t nf = khi - klo;
+    for (uint32_t f = tid; f < nf; f += GRP_BLOCK) lh[f] = 0;
+    __syncthreads();
+    for (uint32_t j = start + tid; j < end; j += GRP_BLOCK) atomicAdd(&lh[tkey[j] - klo], 1u);
+    __syncthreads();
+    // exclusive scan of lh[0..nf): thread t owns the segment [t*per, (t+1)*per)
+    const uint32_t per = (nf + GRP_BLOCK - 1) / GRP_BLOCK;
+    const uint32_t f0 = uint32_t(tid) * per;
+    uint32_t sum = 0;
+    for (uint32_t q = 0; q < per; ++q)
+        if (f0 + q < nf) sum += lh[f0 + q];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, sh, &total) + start;
+    for (uint32_t q = 0; q < per; ++q) {
+        const uint32_t f = f0 + q;
+        if (f < nf) {
+            const uint32_t cnt = lh[f];
+            hist[klo + f] = cnt;
+            offs[klo + f] = run;
+            lh[f] = run;
+            run += cnt;
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = start + tid; j < end; j += GRP_BLOCK) {
+        const uint32_t d = atomicAdd(&lh[tkey[j] - klo], 1u);
+        uint32_t local;
+        double x[3];
+        src.fetch(tval[j], local, x);
+        perm[d] = local;
+        pos_sorted[3 * long(d)] = x[0];
+        pos_sorted[3 * long(d) + 1] = x[1];
+        pos_sorted[3 * long(d) + 2] = x[2];
+    }
+}
+
+// Coarse ranges of a single key space: range c = [c << s, min((c + 1) << s, nb)).
+struct ShiftCoarse {
+    int s;
+    uint32_t nb;
+    __device__ __forceinline__ void range(uint32_t c, uint32_t& lo, uint32_t& hi) const {
+        lo = c << s;
+        hi = min((c + 1) << s, nb);
+    }
+};
+
+// Shift of ShiftCoarse for P particles over nb keys: about `target`
+// particles per coarse range when they are spread evenly, within the LDS
+// bounds of both levels.
+constexpr uint32_t GRP_TARGET = 512;
+
+inline int grp_shift(uint64_t nb, long P, uint64_t target = GRP_TARGET) {
+    int s = 0;
+    // smallest s with at most max(P / target, 1) ranges, then the bounds
+    const uint64_t want = uint64_t(P) / target > 0 ? uint64_t(P) / target : 1;
+    while (((nb + (uint64_t(1) << s) - 1) >> s) > want) ++s;
+    while (((nb + (uint64_t(1) << s) - 1) >> s) > GRP_COARSE_MAX) ++s;
+    // nb <= GRP_COARSE_MAX * GRP_FINE_MAX keeps both bounds
+    while ((uint32_t(1) << s) > GRP_FINE_MAX) --s;
+    return s;
+}
+
+// Host-side plan of a grouping of `nidx` slots (nvalid of them particles)
+// over `ncoarse` coarse ranges.
+struct GrpPlan {
+    long nidx = 0;
+    uint32_t nvalid = 0;
+    uint32_t ncoarse = 0;   // coarse ranges
+    uint32_t fine_max = 0;  // most keys in one coarse range
+    int ipt = 1;            // slots per thread of the coarse passes
+    long nblk = 0;          // blocks of the coarse passes
+    size_t ncounts = 0;     // ncoarse * nblk
+    size_t nsums = 0;       // scan partial sums
+};
+
+inline GrpPlan grp_plan(long nidx, uint32_t nvalid, uint32_t ncoarse, uint32_t fine_max) {
+    GrpPlan g;
+    g.nidx = nidx;
+    g.nvalid = nvalid;
+    g.ncoarse = ncoarse > 0 ? ncoarse : 1;
+    g.fine_max = fine_max;
+    // at least ~512 blocks in the coarse passes, at most 32 slots per thread
+    long ipt = (nidx + long(GRP_BLOCK) * 512 - 1) / (long(GRP_BLOCK) * 512);
+    g.ipt = int(ipt < 1 ? 1 : (ipt > 32 ? 32 : ipt));
+    const long chunk = long(g.ipt) * GRP_BLOCK;
+    g.nblk = (nidx + chunk - 1) / chunk;
+    if (g.nblk == 0) g.nblk = 1;
+    g.ncounts = size_t(g.ncoarse) * size_t(g.nblk);
+    g.nsums = (g.ncounts + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    return g;
+}
+
+// Scratch of a grouping, in uint32 words: key (nidx), tkey and tval (nvalid
+// each), counts and their scan (ncounts each), scan sums (nsums).
+inline size_t grp_scratch_words(const GrpPlan& g) {
+    return size_t(g.nidx) + 2 * size_t(g.nvalid) + 2 * g.ncounts + g.nsums;
+}
+
+// Device buffers of a grouping, carved from its scratch.
+struct GrpBuffers {
+    uint32_t *key, *tkey, *tval, *counts, *gscan, *sums;
+};
+
+inline GrpBuffers grp_buffers(const GrpPlan& g, uint32_t* scratch) {
+    GrpBuffers b;
+    b.key = scratch;
+    b.tkey = b.key + g.nidx;
+    b.tval = b.tkey + g.nvalid;
+    b.counts = b.tval + g.nvalid;
+    b.gscan = b.counts + g.ncounts;
+    b.sums = b.gscan + g.ncounts;
+    return b;
+}
+
+// The three steps of a grouping, enqueued on one stream.  The last writes
+// hist/offs (one entry per key), perm and pos_sorted (nvalid slots each).
+template <typename KeySrc>
+inline void grp_count(const KeySrc& ks, const GrpPlan& g, const GrpBuffers& b, hipStream_t st) {
+    hipLaunchKernelGGL((k_grp_hist<KeySrc>), dim3(unsigned(g.nblk)), dim3(GRP_BLOCK),
+                       size_t(g.ncoarse) * sizeof(uint32_t), st, ks, g.nidx, g.ipt, g.ncoarse, g.nblk, b.key,
+                       b.counts);
+}
+
+inline void grp_scan(const GrpPlan& g, const GrpBuffers& b, hipStream_t st) {
+    const unsigned ns = unsigned(g.nsums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(ns), dim3(SCAN_BLOCK), 0, st, b.counts, long(g.ncounts), b.sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, st, b.sums, int(g.nsums));
+    hipLaunchKernelGGL(k_scan_apply, dim3(ns), dim3(SCAN_BLOCK), 0, st, b.counts, long(g.ncounts), b.sums, b.gscan);
+}
+
+template <typename KeySrc, typename Coarse, typename Src>
+inline void grp_scatter(const KeySrc& ks, const Coarse& cm, const Src& src, const GrpPlan& g, const GrpBuffers& b,
+                        uint32_t* hist, uint32_t* offs, uint32_t* perm, double* pos_sorted, hipStream_t st) {
+    hipLaunchKernelGGL((k_grp_coarse<KeySrc>), dim3(unsigned(g.nblk)), dim3(GRP_BLOCK),
+                       size_t(g.ncoarse) * sizeof(uint32_t), st, ks, b.key, g.nidx, g.ipt, g.ncoarse, g.nblk, b.gscan,
+                       b.tkey, b.tval);
+    hipLaunchKernelGGL((k_grp_fine<Coarse, Src>), dim3(g.ncoarse), dim3(GRP_BLOCK),
+                       size_t(g.fine_max) * sizeof(uint32_t), st, cm, src, b.tkey, b.tval, g.nvalid, g.ncoarse,
+                       g.nblk, b.gscan, hist, offs, perm, pos_sorted);
+}
+
 // ----------------------------------------------------------------- gather ---
 
 template <typename CT>
