@@ -89,7 +89,10 @@ typedef struct bsi_eval_config {
                             16-byte aligned); otherwise, and for 1, one thread per particle
                             reading the grid directly */
     int32_t tiles_per_group; /* consecutive Morton tiles walked by one tiled workgroup (0 = 4) */
-    int32_t reserved[3];     /* must be 0 */
+    int32_t tile_block;      /* threads per workgroup of the tiled gather with 8^3-cell tiles:
+                                0 or 64 = one wavefront per tile, 256 = four wavefronts share a
+                                tile (dense tiles); other tile sizes have a fixed block */
+    int32_t reserved[2];     /* must be 0 */
 } bsi_eval_config;
 
 typedef struct bsi_ctx bsi_ctx;

@@ -30,7 +30,8 @@ class FieldDesc(ctypes.Structure):
 class EvalConfig(ctypes.Structure):
     _fields_ = [("sort_tile", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("tiles_per_group", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("tiles_per_group", ctypes.c_int32), ("tile_block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class ServerConfig(ctypes.Structure):

@@ -137,11 +137,21 @@ constexpr int tile_block() {
 }
 
 template <int N, typename CT, int C, int T>
-bool launch_tiled_T(const GatherArgs& ga, bool grad, unsigned nb, hipStream_t s) {
+bool launch_tiled_T(const GatherArgs& ga, bool grad, bool wide, unsigned nb, hipStream_t s) {
     if constexpr (!tile_ok<N, CT, C, T>()) {
         return false;
     } else {
         constexpr int B = tile_block<N, CT, C, T>();
+        if constexpr (T == 8 && B == 64) {
+            // dense 8^3 tiles: four wavefronts share one LDS block
+            if (wide) {
+                if (grad)
+                    hipLaunchKernelGGL((k_gather_tiled<N, CT, C, true, T, 256>), dim3(nb), dim3(256), 0, s, ga);
+                else
+                    hipLaunchKernelGGL((k_gather_tiled<N, CT, C, false, T, 256>), dim3(nb), dim3(256), 0, s, ga);
+                return true;
+            }
+        }
         if (grad)
             hipLaunchKernelGGL((k_gather_tiled<N, CT, C, true, T, B>), dim3(nb), dim3(B), 0, s, ga);
         else
@@ -151,22 +161,25 @@ bool launch_tiled_T(const GatherArgs& ga, bool grad, unsigned nb, hipStream_t s)
 }
 
 template <int N, typename CT, int C>
-bool launch_tiled_c(int T, const GatherArgs& ga, bool grad, unsigned nb, hipStream_t s) {
+bool launch_tiled_c(int T, const GatherArgs& ga, bool grad, bool wide, unsigned nb, hipStream_t s) {
     switch (T) {
-        case 4: return launch_tiled_T<N, CT, C, 4>(ga, grad, nb, s);
-        case 6: return launch_tiled_T<N, CT, C, 6>(ga, grad, nb, s);
-        case 8: return launch_tiled_T<N, CT, C, 8>(ga, grad, nb, s);
-        case 12: return launch_tiled_T<N, CT, C, 12>(ga, grad, nb, s);
-        case 16: return launch_tiled_T<N, CT, C, 16>(ga, grad, nb, s);
+        case 4: return launch_tiled_T<N, CT, C, 4>(ga, grad, wide, nb, s);
+        case 6: return launch_tiled_T<N, CT, C, 6>(ga, grad, wide, nb, s);
+        case 8: return launch_tiled_T<N, CT, C, 8>(ga, grad, wide, nb, s);
+        case 12: return launch_tiled_T<N, CT, C, 12>(ga, grad, wide, nb, s);
+        case 16: return launch_tiled_T<N, CT, C, 16>(ga, grad, wide, nb, s);
         default: return false;
     }
 }
 
 template <typename CT>
-bool launch_tiled_ct(int N, int C, int T, const GatherArgs& ga, bool grad, unsigned nb, hipStream_t s) {
+bool launch_tiled_ct(int N, int C, int T, const GatherArgs& ga, bool grad, bool wide, unsigned nb,
+                     hipStream_t s) {
     if (N == 4)
-        return C == 1 ? launch_tiled_c<4, CT, 1>(T, ga, grad, nb, s) : launch_tiled_c<4, CT, 3>(T, ga, grad, nb, s);
-    return C == 1 ? launch_tiled_c<6, CT, 1>(T, ga, grad, nb, s) : launch_tiled_c<6, CT, 3>(T, ga, grad, nb, s);
+        return C == 1 ? launch_tiled_c<4, CT, 1>(T, ga, grad, wide, nb, s)
+                      : launch_tiled_c<4, CT, 3>(T, ga, grad, wide, nb, s);
+    return C == 1 ? launch_tiled_c<6, CT, 1>(T, ga, grad, wide, nb, s)
+                  : launch_tiled_c<6, CT, 3>(T, ga, grad, wide, nb, s);
 }
 
 template <int N, typename CT, int C>
@@ -268,6 +281,8 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
     int block = cfg.block > 0 ? cfg.block : 256;
     BSI_CHECK(block % 64 == 0 && block >= 64 && block <= 256, BSI_E_INVAL,
               "eval block must be 64, 128, 192 or 256");
+    BSI_CHECK(cfg.tile_block == 0 || cfg.tile_block == 64 || cfg.tile_block == 256, BSI_E_INVAL,
+              "tile_block must be 0, 64 or 256");
     const uint32_t* perm = nullptr;
     const double* pos_sorted = nullptr;
     const uint32_t* hist = nullptr;
@@ -314,9 +329,11 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
     if (tiled) {
         const unsigned nb = unsigned((nbf + 1 + ga.tiles_per_group - 1) / ga.tiles_per_group);
         bool ok = false;
-        if (f->desc.coef == BSI_F64) ok = launch_tiled_ct<double>(f->N, f->C, tile, ga, g, nb, s);
-        else if (f->desc.coef == BSI_F32) ok = launch_tiled_ct<float>(f->N, f->C, tile, ga, g, nb, s);
-        else ok = launch_tiled_ct<uint16_t>(f->N, f->C, tile, ga, g, nb, s);
+        // tile_block 256 asks for four wavefronts per 8^3 tile (dense tiles)
+        const bool wide = cfg.tile_block == 256;
+        if (f->desc.coef == BSI_F64) ok = launch_tiled_ct<double>(f->N, f->C, tile, ga, g, wide, nb, s);
+        else if (f->desc.coef == BSI_F32) ok = launch_tiled_ct<float>(f->N, f->C, tile, ga, g, wide, nb, s);
+        else ok = launch_tiled_ct<uint16_t>(f->N, f->C, tile, ga, g, wide, nb, s);
         BSI_CHECK(ok, BSI_E_UNSUPPORTED, "no tiled gather instance for this tile size");
     } else {
         const unsigned nb = unsigned((P + block - 1) / block);

@@ -614,19 +614,27 @@ __device__ __forceinline__ void contract_and_store(const GatherArgs& a, long p, 
 // Geometry of one LDS tile: the (T+N-1)^3 block of the ghost-padded grid that
 // holds the stencils of a T^3 tile of cells, each row of (T+N-1)*C elements
 // rounded up to whole 16-byte chunks.
-template <int N, typename CT, int C, int T>
-struct TileGeom {
-    static constexpr int R = T + N - 1;
-    static constexpr int VEC = 16 / int(sizeof(CT));   // elements per 16-byte chunk
-    static constexpr int CH = (R * C + VEC - 1) / VEC;  // chunks per row
-    static constexpr int LROW = CH * VEC;               // LDS row pitch (elements)
-    static constexpr int ROWS = R * R;
+// LDS copy of the (T0+N-1) x (T1+N-1) x (T2+N-1) block of grid points that
+// the particles of a T0 x T1 x T2 cell box read: rows along axis 2, each
+// padded to whole 16-byte chunks.
+template <int N, typename CT, int C, int T0, int T1, int T2>
+struct BlockGeom {
+    static constexpr int R0 = T0 + N - 1;
+    static constexpr int R1 = T1 + N - 1;
+    static constexpr int R2 = T2 + N - 1;
+    static constexpr int VEC = 16 / int(sizeof(CT));    // elements per 16-byte chunk
+    static constexpr int CH = (R2 * C + VEC - 1) / VEC;  // chunks per row
+    static constexpr int LROW = CH * VEC;                // LDS row pitch (elements)
+    static constexpr int ROWS = R0 * R1;
     static constexpr int SLOTS = ROWS * CH;
-    static constexpr int PER = (SLOTS + 63) / 64;       // chunks per lane
     static constexpr int BYTES = SLOTS * 16;
-    // tile origins must start on 16-byte boundaries inside a row
-    static constexpr bool ALIGNED = (T * C * int(sizeof(CT))) % 16 == 0;
+    // block origins must start on 16-byte boundaries inside a row
+    static constexpr bool ALIGNED = (T2 * C * int(sizeof(CT))) % 16 == 0;
 };
+
+// Cubic Morton tiles of T^3 cells.
+template <int N, typename CT, int C, int T>
+using TileGeom = BlockGeom<N, CT, C, T, T, T>;
 
 // 16 bytes as a native vector (loads and stores of it are single instructions,
 // never aggregate copies) and a load of it from global memory.
@@ -655,25 +663,21 @@ __device__ __forceinline__ uint32_t next_tile(const GatherArgs& a, uint32_t b, u
     return b;
 }
 
-// Addressing of the LDS block of tile `bucket` in the ghost-padded grid.
-// Rows outside the padded grid (partial tiles only; never read by a particle)
-// load the tile origin instead; chunks past a row's end read the next row or
-// the allocation's slack.
-template <int N, typename CT, int C, int T>
+// Addressing of the LDS block with cell origin (o0, o1, o2) in the
+// ghost-padded grid.  Rows outside the padded grid (partial blocks only; never
+// read by a particle) load the block origin instead; chunks past a row's end
+// read the next row or the allocation's slack.
+template <int N, typename CT, int C, typename G>
 struct TileLoad {
-    using G = TileGeom<N, CT, C, T>;
     const u32x4* g;
     int p0v, p1v, lim0, lim1;
 
-    __device__ __forceinline__ TileLoad(const GatherArgs& a, uint32_t bucket) {
-        const int o0 = int(compact3(bucket >> 2)) * T;
-        const int o1 = int(compact3(bucket >> 1)) * T;
-        const int o2 = int(compact3(bucket)) * T;
+    __device__ __forceinline__ TileLoad(const GatherArgs& a, int o0, int o1, int o2) {
         lim0 = a.n0 + N - 1 - o0;
         lim1 = a.n1 + N - 1 - o1;
         g = reinterpret_cast<const u32x4*>(static_cast<const CT*>(a.grid) +
                                            (long(o0) * a.P1 + o1) * long(a.pitch2) + long(o2) * C);
-        p1v = a.pitch2 / G::VEC;  // row pitch in chunks (offsets inside a tile stay < 2^31)
+        p1v = a.pitch2 / G::VEC;  // row pitch in chunks (offsets inside a block stay < 2^31)
         p0v = a.P1 * p1v;
     }
 };
@@ -712,24 +716,32 @@ __device__ __forceinline__ void direct_eval(const GatherArgs& a, long j, bool st
     }
 }
 
-// LDS bytes one workgroup of B threads needs for tiles of T^3 cells.
-template <int N, typename CT, int C, int T, int B>
-constexpr int tile_lds_bytes() {
-    return (TileGeom<N, CT, C, T>::SLOTS + B - 1) / B * B * 16;
+// LDS bytes one workgroup of B threads needs for the block geometry G.
+template <typename G, int B>
+constexpr int block_lds_bytes() {
+    return (G::SLOTS + B - 1) / B * B * 16;
 }
 
-// The cells of tile `cur` (count particles from binned slot start): see tile_eval.
-template <int N, typename CT, int C, bool GRAD, int T, int B>
-__device__ __forceinline__ void tile_eval_cells(const GatherArgs& a, uint32_t cur, uint32_t count, uint32_t start,
-                                                u32x4* tile_v) {
+template <int N, typename CT, int C, int T, int B>
+constexpr int tile_lds_bytes() {
+    return block_lds_bytes<TileGeom<N, CT, C, T>, B>();
+}
+
+// The `count` particles from binned slot `start`, all with cells inside the
+// box of geometry G at cell origin (o0, o1, o2), evaluated by one workgroup
+// of B threads from an LDS copy of the box's block of the grid.  All 16-byte
+// loads of the block are issued at once (one memory round trip) straight into
+// `lds` (block_lds_bytes() of it).  Two lanes per particle (one half of the
+// axis-0 sum each, combined with a lane shuffle) when the box holds at most
+// B/2 particles, one lane per particle otherwise.  Every thread of the
+// workgroup calls this with the same arguments.
+template <int N, typename CT, int C, bool GRAD, typename G, int B>
+__device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, int o1, int o2, uint32_t count,
+                                                 uint32_t start, u32x4* lds) {
     using AT = typename Acc<CT>::type;
-    using G = TileGeom<N, CT, C, T>;
     constexpr int PERB = (G::SLOTS + B - 1) / B;
-    const CT* tile = reinterpret_cast<const CT*>(tile_v);
+    const CT* tile = reinterpret_cast<const CT*>(lds);
     const int tid = threadIdx.x;
-    const int o0 = int(compact3(cur >> 2)) * T;
-    const int o1 = int(compact3(cur >> 1)) * T;
-    const int o2 = int(compact3(cur)) * T;
     const bool pair = count <= uint32_t(B / 2);
     const int stride = pair ? B / 2 : B;
     const uint32_t jlane = pair ? uint32_t(tid >> 1) : uint32_t(tid);
@@ -739,18 +751,18 @@ __device__ __forceinline__ void tile_eval_cells(const GatherArgs& a, uint32_t cu
         // DMA path of the load unit (no registers hold the data): each
         // wavefront's instruction q fills 64 consecutive 16-byte slots
         // starting at its wave-uniform LDS base
-        TileLoad<N, CT, C, T> tl(a, cur);
+        TileLoad<N, CT, C, G> tl(a, o0, o1, o2);
         const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
 #pragma unroll
         for (int q = 0; q < PERB; ++q) {
             const int sl = q * B + tid;
             const int row = sl / G::CH;
             const int ch = sl - row * G::CH;
-            const int r0 = row / G::R;
-            const int r1 = row - r0 * G::R;
+            const int r0 = row / G::R1;
+            const int r1 = row - r0 * G::R1;
             const bool ok = sl < G::SLOTS && r0 < tl.lim0 && r1 < tl.lim1;
             __builtin_amdgcn_global_load_lds((global_u32x4*)(tl.g + (ok ? r0 * tl.p0v + r1 * tl.p1v + ch : 0)),
-                                             (__attribute__((address_space(3))) void*)(tile_v + q * B + wbase),
+                                             (__attribute__((address_space(3))) void*)(lds + q * B + wbase),
                                              16, 0, 0);
         }
         __builtin_amdgcn_s_waitcnt(0);  // every counter at zero: the block is in LDS
@@ -758,7 +770,7 @@ __device__ __forceinline__ void tile_eval_cells(const GatherArgs& a, uint32_t cu
     lds_barrier();
     for (uint32_t j0 = 0; j0 < count; j0 += uint32_t(stride)) {
         // a wavefront without any particle in this round skips it (uniform);
-        // inside a working wavefront, lanes past the end evaluate the tile's
+        // inside a working wavefront, lanes past the end evaluate the box's
         // first particle and store nothing
         if (j0 + uint32_t((pair ? 32 : 64) * (tid / 64)) >= count) continue;
         const uint32_t j = j0 + jlane;
@@ -770,8 +782,8 @@ __device__ __forceinline__ void tile_eval_cells(const GatherArgs& a, uint32_t cu
         int cell[3];
         AT w[3][N], wd[3][N];
         particle_setup_x<N, AT>(a, x, cell, w, wd);  // finite by construction of the bucket
-        const CT* base = tile + ((cell[0] - o0) * G::R + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * C;
-        auto rows = [base](int ia, int ib) { return base + (ia * G::R + ib) * G::LROW; };
+        const CT* base = tile + ((cell[0] - o0) * G::R1 + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * C;
+        auto rows = [base](int ia, int ib) { return base + (ia * G::R1 + ib) * G::LROW; };
         if (pair) {
             // both lanes of a pair run the same instructions: lane `half`
             // takes planes half*N/2 .. half*N/2 + N/2 - 1
@@ -804,28 +816,32 @@ __device__ __forceinline__ void tile_eval_cells(const GatherArgs& a, uint32_t cu
     lds_barrier();
 }
 
+// NaN outputs for the `count` particles without a cell (the last bucket),
+// which are also counted.
+template <typename AT, int C, bool GRAD, int B>
+__device__ __forceinline__ void nonfinite_eval(const GatherArgs& a, uint32_t count, uint32_t start) {
+    for (uint32_t j = threadIdx.x; j < count; j += B) write_nan<AT, C, GRAD>(a, long(a.perm[start + j]));
+    if (threadIdx.x == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
+}
+
 // All particles of Morton tile `cur` (T^3 cells) evaluated by one workgroup of
-// B threads from an LDS copy of the tile's (T+N-1)^3 block of the grid.  All
-// 16-byte loads of the block are issued at once (one memory round trip)
-// straight into `tile_v` (tile_lds_bytes() of LDS); the tile's binned
-// positions are contiguous.  Two lanes per particle (one half of the axis-0 sum each,
-// combined with a lane shuffle) while the tile holds at most B/2 particles,
-// one lane per particle otherwise.  `cur` == nbuckets_finite is the bucket of
-// particles without a cell: they get NaN outputs and are counted.  Every
-// thread of the workgroup must call this with the same `cur`.
+// B threads (block_eval_cells).  `cur` == nbuckets_finite is the bucket of
+// particles without a cell.  Every thread of the workgroup must call this
+// with the same `cur`.
 template <int N, typename CT, int C, bool GRAD, int T, int B>
 __device__ __forceinline__ void tile_eval(const GatherArgs& a, uint32_t cur, u32x4* tile_v) {
     using AT = typename Acc<CT>::type;
-    const int tid = threadIdx.x;
     // every value that steers a loop or branch holding a barrier is made
     // wave-uniform explicitly, so that those loops are scalar
     const uint32_t count = __builtin_amdgcn_readfirstlane(a.hist[cur]);
     const uint32_t start = __builtin_amdgcn_readfirstlane(a.offs[cur]);
     if (cur == a.nbuckets_finite) {
-        for (uint32_t j = tid; j < count; j += B) write_nan<AT, C, GRAD>(a, long(a.perm[start + j]));
-        if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
+        nonfinite_eval<AT, C, GRAD, B>(a, count, start);
     } else {
-        tile_eval_cells<N, CT, C, GRAD, T, B>(a, cur, count, start, tile_v);
+        const int o0 = int(compact3(cur >> 2)) * T;
+        const int o1 = int(compact3(cur >> 1)) * T;
+        const int o2 = int(compact3(cur)) * T;
+        block_eval_cells<N, CT, C, GRAD, TileGeom<N, CT, C, T>, B>(a, o0, o1, o2, count, start, tile_v);
     }
 }
 

@@ -59,10 +59,11 @@ def test_gather_matches_oracle(ctx, n, C, N, coef):
         back = host(f.get_coefficients())
         assert np.array_equal(back, stored)
         for cfg in (None, (0, 256, 0, 0), (4, 128, 1, 0), (8, 64, 1, 0), (2, 192, 0, 0),
-                    (6, 256, 1, 0), (12, 128, 1, 0), (8, 256, 1, 1), (16, 256, 1, 0)):
+                    (6, 256, 1, 0), (12, 128, 1, 0), (8, 256, 1, 1), (16, 256, 1, 0), (8, 256, 1, 0, 256)):
             c = None
             if cfg is not None:
-                c = bsi.EvalConfig(sort_tile=cfg[0], block=cfg[1], xcd_remap=cfg[2], variant=cfg[3])
+                c = bsi.EvalConfig(sort_tile=cfg[0], block=cfg[1], xcd_remap=cfg[2], variant=cfg[3],
+                                   tile_block=cfg[4] if len(cfg) > 4 else 0)
             u, g = f.eval(dev(pos), cfg=c)
             u, g = host(u), host(g)
             eu, eg = rel_err(u, want_u), rel_err(g, want_g)
@@ -81,9 +82,9 @@ def test_gather_results_independent_of_tuning(ctx):
         f.set_coefficients(dev(grid))
         ref = None
         for tile in (0, 1, 2, 4, 6, 8, 10, 12, 16, 32):
-            for block, variant in ((64, 0), (256, 0), (128, 1)):
+            for block, variant, tb in ((64, 0, 0), (256, 0, 0), (128, 1, 0), (256, 0, 256)):
                 u, g = f.eval(dev(pos), cfg=bsi.EvalConfig(sort_tile=tile, block=block, xcd_remap=1,
-                                                           variant=variant))
+                                                           variant=variant, tile_block=tb))
                 cur = (host(u), host(g))
                 if ref is None:
                     ref = cur
@@ -128,6 +129,8 @@ def test_eval_rejects_bad_arguments(ctx):
         host_pos = torch.zeros((4, 3), dtype=torch.float64)
         with pytest.raises(bsi.BsiError):
             _bsi.bsi_eval(f.handle, host_pos, 4, u)
+        with pytest.raises(bsi.BsiError):
+            f.eval(pos, cfg=bsi.EvalConfig(sort_tile=8, block=256, xcd_remap=1, tile_block=128))
     for bad in (dict(order=5), dict(order=8), dict(n=(30, 32, 32)), dict(n=(10, 32, 32)),
                 dict(ncomp=2), dict(n=(2048, 32, 32))):
         kw = dict(n=(32, 32, 32), ncomp=1, order=4)
