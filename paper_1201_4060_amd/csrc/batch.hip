@@ -103,7 +103,7 @@ struct BatchSlots {
         const BatchItem& it = item_of(i, p);
         return it.cbase + ((k - it.bbase) >> it.cshift);
     }
-    __device__ __forceinline__ void fetch(uint32_t i, uint32_t& local, double* x) const {
+    __device__ __forceinline__ void fetch(long i, uint32_t& local, double* x) const {
         long p;
         const BatchItem& it = item_of(i, p);
         local = uint32_t(p);
@@ -306,7 +306,7 @@ static bsi_status enqueue(bsi_batch* b, hipStream_t s) {
         const BatchSlots slots{a.items, a.pblock_item};
         grp_count(slots, b->grp, b->gbuf, s);
         grp_scan(b->grp, b->gbuf, s);
-        grp_scatter(slots, TableCoarse{a.cstart}, slots, b->grp, b->gbuf, a.hist, a.offs, a.perm, a.pos_sorted, s);
+        grp_scatter(slots, TableCoarse{a.cstart}, b->grp, b->gbuf, a.hist, a.offs, a.perm, a.pos_sorted, s);
         if (b->nbblocks) hipLaunchKernelGGL(k_batch_compact, dim3(b->nbblocks), dim3(BLK), 0, s, a);
     }
     {
@@ -459,7 +459,8 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
         set_error("too many buckets in one batch; use coarser sort tiles");
         return BSI_E_INVAL;
     }
-    b->grp = grp_plan(long(pblock.size()) * BLK, uint32_t(pbase), uint32_t(cstart.size() - 1), fine_max);
+    b->grp = grp_plan(long(pblock.size()) * BLK, uint32_t(pbase), uint32_t(Btot), uint32_t(cstart.size() - 1),
+                      fine_max);
     b->nitems = int(hi.size());
     b->Ptot = pbase;
     b->Btot = Btot;

@@ -33,6 +33,12 @@ struct MortonKey {
     uint32_t nbuckets_finite;
     int shift;
     __device__ __forceinline__ uint32_t coarse(long, uint32_t k) const { return k >> shift; }
+    __device__ __forceinline__ void fetch(long p, uint32_t& local, double* x) const {
+        local = uint32_t(p);
+        x[0] = a.pos[3 * p];
+        x[1] = a.pos[3 * p + 1];
+        x[2] = a.pos[3 * p + 2];
+    }
     __device__ __forceinline__ bool key(long p, uint32_t& k, uint32_t& cr) const {
         const int n[3] = {a.n0, a.n1, a.n2};
         const double ih[3] = {a.ih0, a.ih1, a.ih2};
@@ -47,17 +53,6 @@ struct MortonKey {
                 spread3(uint32_t(c[2] / tile));
         cr = k >> shift;
         return true;
-    }
-};
-
-// Positions of one particle array, slot i = particle i.
-struct ArrayPositions {
-    const double* pos;
-    __device__ __forceinline__ void fetch(uint32_t i, uint32_t& local, double* x) const {
-        local = i;
-        x[0] = pos[3 * long(i)];
-        x[1] = pos[3 * long(i) + 1];
-        x[2] = pos[3 * long(i) + 2];
     }
 };
 
@@ -213,24 +208,41 @@ size_t bin_bucket_count(const bsi_field* f, int tile) {
     return size_t(1) << (3 * bits);
 }
 
-// Bucket arrays live at the start of the binning scratch: hist[nb], offs[nb],
-// then the grouping scratch.  At most 2^24 + 1 keys (effective_tile).
+// At most 2^24 + 1 keys (effective_tile).
 static GrpPlan bin_plan(const bsi_field* f, long P, int tile, int* shift) {
     const uint64_t nb = bin_bucket_count(f, tile) + 1;
     *shift = grp_shift(nb, P);
     const uint32_t ncoarse = uint32_t((nb + (uint64_t(1) << *shift) - 1) >> *shift);
-    return grp_plan(P, uint32_t(P), ncoarse, uint32_t(1) << *shift);
+    return grp_plan(P, uint32_t(P), uint32_t(nb), ncoarse, uint32_t(std::min<uint64_t>(nb, uint64_t(1) << *shift)));
 }
 
-bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, uint32_t* perm, void* scratch,
-                   double* pos_sorted, hipStream_t s) {
+// Workspace of a binned evaluation (16-byte aligned): the grouping scratch,
+// then the binned positions (3P doubles), the permutation (P), the bucket
+// counts and first slots (nb each).
+struct BinLayout {
+    size_t grp, pos, perm, hist, offs, bytes;
+};
+
+static BinLayout bin_layout(const bsi_field* f, long P, int tile) {
+    int shift = 0;
+    const size_t nb = bin_bucket_count(f, tile) + 1;
+    BinLayout l;
+    l.grp = 0;
+    l.pos = (grp_scratch_words(bin_plan(f, P, tile, &shift)) * sizeof(uint32_t) + 15) / 16 * 16;
+    l.perm = l.pos + 3 * size_t(P) * sizeof(double);
+    l.hist = l.perm + size_t(P) * sizeof(uint32_t);
+    l.offs = l.hist + nb * sizeof(uint32_t);
+    l.bytes = l.offs + nb * sizeof(uint32_t);
+    return l;
+}
+
+bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, void* scratch, uint32_t* perm,
+                   double* pos_sorted, uint32_t* hist, uint32_t* offs, hipStream_t s) {
     const size_t nbf = bin_bucket_count(f, tile);
     const size_t nb = nbf + 1;
     int shift = 0;
     const GrpPlan g = bin_plan(f, P, tile, &shift);
-    uint32_t* hist = static_cast<uint32_t*>(scratch);
-    uint32_t* offs = hist + nb;
-    const GrpBuffers gb = grp_buffers(g, offs + nb);
+    const GrpBuffers gb = grp_buffers(g, static_cast<uint32_t*>(scratch));
     const MortonKey mk{cell_args(f, pos, P), tile, uint32_t(nbf), shift};
     {
         StageTimer tm(f->ctx, "bin_count", s);
@@ -242,17 +254,10 @@ bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, uint32_t* 
     }
     {
         StageTimer tm(f->ctx, "bin_scatter", s);
-        grp_scatter(mk, ShiftCoarse{shift, uint32_t(nb)}, ArrayPositions{pos}, g, gb, hist, offs, perm, pos_sorted,
-                    s);
+        grp_scatter(mk, ShiftCoarse{shift, uint32_t(nb)}, g, gb, hist, offs, perm, pos_sorted, s);
     }
     BSI_HIP(hipGetLastError());
     return BSI_OK;
-}
-
-size_t bin_scratch_bytes(const bsi_field* f, long P, int tile) {
-    const size_t nb = bin_bucket_count(f, tile) + 1;
-    int shift = 0;
-    return (2 * nb + grp_scratch_words(bin_plan(f, P, tile, &shift))) * sizeof(uint32_t);
 }
 
 bool tiled_supported(const bsi_field* f, int tile) {
@@ -272,7 +277,7 @@ static int effective_tile(const bsi_field* f, const bsi_eval_config& cfg) {
 size_t eval_ws_bytes(const bsi_field* f, int64_t P, const bsi_eval_config& cfg) {
     const int tile = effective_tile(f, cfg);
     if (tile == 0 || P == 0) return 0;
-    return 3 * size_t(P) * sizeof(double) + size_t(P) * sizeof(uint32_t) + bin_scratch_bytes(f, P, tile);
+    return bin_layout(f, P, tile).bytes;
 }
 
 bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
@@ -290,15 +295,20 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
     const int tile = effective_tile(f, cfg);
     size_t nbf = 0;
     if (tile > 0) {
-        BSI_CHECK(ws != nullptr, BSI_E_INVAL, "binned evaluation needs a workspace");
-        double* ps = static_cast<double*>(ws);
-        uint32_t* pm = reinterpret_cast<uint32_t*>(ps + 3 * size_t(P));
-        BSI_TRY(bin_run(f, pos, P, tile, pm, pm + P, ps, s));
+        BSI_CHECK(ws != nullptr && reinterpret_cast<uintptr_t>(ws) % 16 == 0, BSI_E_INVAL,
+                  "binned evaluation needs a 16-byte aligned workspace");
+        const BinLayout l = bin_layout(f, P, tile);
+        char* w = static_cast<char*>(ws);
+        double* ps = reinterpret_cast<double*>(w + l.pos);
+        uint32_t* pm = reinterpret_cast<uint32_t*>(w + l.perm);
+        uint32_t* hs = reinterpret_cast<uint32_t*>(w + l.hist);
+        uint32_t* os = reinterpret_cast<uint32_t*>(w + l.offs);
+        BSI_TRY(bin_run(f, pos, P, tile, w + l.grp, pm, ps, hs, os, s));
         perm = pm;
         pos_sorted = ps;
-        hist = pm + P;
+        hist = hs;
+        offs = os;
         nbf = bin_bucket_count(f, tile);
-        offs = hist + nbf + 1;
     }
     GatherArgs ga;
     ga.grid = f->grid;

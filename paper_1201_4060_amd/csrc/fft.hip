@@ -18,10 +18,21 @@
 // consecutive elements.
 #include "common.hpp"
 
-// LDS budget (KiB) of one strided-pass workgroup's line block
+// LDS budget (KiB) of one strided-pass workgroup's line block: two blocks per
+// CU (160 KB of LDS), so 32 lines of 256 FP32 points or 16 lines of 512
 #ifndef BSI_FFT_LDS_KB
-#define BSI_FFT_LDS_KB 68
+#define BSI_FFT_LDS_KB 80
 #endif
+// The first pass reads the caller's spectrum (FP64 pairs, planes of 2 MB and
+// more apart for lines of 512 points and longer): there, blocks of 32 lines
+// (one per CU) give 512-byte row segments instead of 256.
+#ifndef BSI_FFT_LDS_KB_LONG_FIRST
+#define BSI_FFT_LDS_KB_LONG_FIRST 150
+#endif
+template <int LEN, bool FIRST>
+constexpr int strided_lds_kb() {
+    return (FIRST && LEN >= 512) ? BSI_FFT_LDS_KB_LONG_FIRST : BSI_FFT_LDS_KB;
+}
 
 namespace bsi {
 
@@ -133,7 +144,7 @@ __device__ __forceinline__ void fft_stages(cplx<T>* buf, const cplx<T>* tw, int 
     }
 }
 
-// Lines per workgroup for the strided passes: keep the LDS line block near 33 KB.
+// Lines per workgroup for the strided passes, within BSI_FFT_LDS_KB of LDS.
 // W lines per workgroup (longer contiguous row segments of the strided axis
 // are better for HBM), TEAM threads per line; TEAM divides LEN so that each
 // thread moves a fixed line and a fixed set of rows.  The line block plus the
@@ -144,10 +155,10 @@ __device__ __forceinline__ void fft_stages(cplx<T>* buf, const cplx<T>* tw, int 
 #ifndef BSI_FFT_THREADS
 #define BSI_FFT_THREADS 512
 #endif
-template <typename T, int LEN>
+template <typename T, int LEN, int KB = BSI_FFT_LDS_KB>
 struct StridedCfg {
     static constexpr int bytes = int(sizeof(cplx<T>));
-    static constexpr int raw = (BSI_FFT_LDS_KB * 1024 - LEN * bytes) / ((LEN + 1) * bytes);
+    static constexpr int raw = (KB * 1024 - LEN * bytes) / ((LEN + 1) * bytes);
     static constexpr int W = raw >= 32 && BSI_FFT_WMAX >= 32 ? 32
                              : raw >= 16 && BSI_FFT_WMAX >= 16 ? 16
                              : raw >= 8 ? 8 : raw >= 4 ? 4 : 2;
@@ -166,7 +177,7 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
                                                   long sOther, long sComp, const double* cAxis,
                                                   const double* cOther, const double* c2,
                                                   const cplx<T>* twg) {
-    using Cfg = StridedCfg<T, LEN>;
+    using Cfg = StridedCfg<T, LEN, strided_lds_kb<LEN, FIRST>()>;
     constexpr int W = Cfg::W;
     constexpr int LP = LEN + 1;
     __shared__ cplx<T> lines[W * LP];
@@ -398,9 +409,10 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
                        const cplx<T>* tw, hipStream_t s, int* Wout) {
 #define BSI_AXIS_CASE(L)                                                                           \
     case L: {                                                                                      \
-        *Wout = StridedCfg<T, L>::W;                                                               \
-        grid.x = (H + StridedCfg<T, L>::W - 1) / StridedCfg<T, L>::W;                              \
-        hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), grid, dim3(StridedCfg<T, L>::THREADS), 0, s, in, out, H, sAxis, \
+        using Cfg = StridedCfg<T, L, strided_lds_kb<L, FIRST>()>;                                  \
+        *Wout = Cfg::W;                                                                            \
+        grid.x = (H + Cfg::W - 1) / Cfg::W;                                                        \
+        hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), grid, dim3(Cfg::THREADS), 0, s, in, out, H, sAxis, \
                            sOther, sComp, cAxis, cOther, c2, tw);                                  \
         break;                                                                                     \
     }

@@ -148,6 +148,15 @@ static __global__ void k_fill_u32(uint32_t* p, long n, uint32_t v) {
         p[i] = v;
 }
 
+// 16 bytes as a native vector (loads and stores of it are single instructions,
+// never aggregate copies) and a load of it from global memory.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u32x4 global_u32x4;
+
+__device__ __forceinline__ u32x4 load_global16(const u32x4* p) {
+    return *(global_u32x4*)p;
+}
+
 // ------------------------------------------------------- grouping by key ---
 // Particles are grouped by bucket key with a two-level counting sort that uses
 // no global atomics (their throughput, not the data volume, bounds a one-pass
@@ -159,27 +168,44 @@ static __global__ void k_fill_u32(uint32_t* p, long n, uint32_t v) {
 //                 LDS; the counts are stored range-major
 //   (scan)        exclusive scan of the counts: where each block's particles
 //                 of each coarse range go
-//   k_grp_coarse  each block scatters (key, slot) into the coarse ranges
-//   k_grp_fine    one workgroup per coarse range: LDS histogram of its keys,
-//                 the bucket table (count and first binned slot of every key
-//                 of the range, empty keys included, so the table needs no
-//                 clearing) and the final scatter of the permutation and the
-//                 binned positions.
-// The order inside a bucket is whatever the LDS atomics give; no result
-// depends on it.  Blocks of the two coarse passes are mapped so that each XCD
-// takes one contiguous range of slots, which keeps the partial-line writes of
-// one coarse range in one L2.
+//   k_grp_coarse  each block scatters (key, slot) into the coarse ranges (and
+//                 clears the per-key counters of the next steps)
+//   k_grp_plan    one workgroup: each coarse range is cut into chunks of
+//                 GRP_CHUNK particles (a crowded range gets many), listed
+//                 range by range
+//   k_grp_chunk_count  one workgroup per chunk: LDS histogram of its keys,
+//                 added to the per-key counters (one atomic per key present)
+//   k_grp_table   one workgroup per coarse range: the bucket table (count and
+//                 first binned slot of every key of the range, empty keys
+//                 included, so the table needs no clearing), and the counters
+//                 turned into per-key cursors
+//   k_grp_chunk_scatter  one workgroup per chunk: reserves each key's slots
+//                 with one atomic on its cursor, then writes the permutation
+//                 and the binned positions.
+// The order inside a bucket is whatever the atomics give; no result depends
+// on it.  Blocks of the two coarse passes are mapped so that each XCD takes
+// one contiguous range of slots, which keeps the partial-line writes of one
+// coarse range in one L2.
 //
 // KeySrc::key(i, &k, &c) gives the key and coarse range of grouping slot i,
 // or false for a slot that holds no particle (padding); KeySrc::coarse(i, k)
-// gives the coarse range of slot i's key k again.  Coarse::range(c, &lo, &hi)
-// gives the keys [lo, hi) of range c.  Src::fetch(i, &local, x) gives the
-// particle of slot i: its index in its own position array and its position.
+// gives the coarse range of slot i's key k again; KeySrc::fetch(i, &local, x)
+// gives the particle of slot i: its index in its own position array and its
+// position.  Coarse::range(c, &lo, &hi) gives the keys [lo, hi) of range c.
 
 constexpr int GRP_BLOCK = SCAN_BLOCK;
 constexpr uint32_t GRP_FINE_MAX = 8192;      // keys per coarse range: 32 KB of LDS
 constexpr uint32_t GRP_COARSE_MAX = 8192;    // coarse ranges: 32 KB of LDS
 constexpr uint32_t GRP_NONE = 0xffffffffu;
+constexpr uint32_t GRP_CHUNK = 2048;         // particles per chunk of the fine passes
+
+// A particle on its way to its bucket: key, index in its own position array
+// and position, 32 bytes (written and read as two 16-byte vectors).
+struct alignas(16) GrpRec {
+    uint32_t key, local;
+    double x[3];
+};
+static_assert(sizeof(GrpRec) == 32, "grouping record is two 16-byte vectors");
 
 __device__ __forceinline__ uint32_t grp_block(long nblk) {
     const long b = blockIdx.x;
@@ -217,9 +243,11 @@ template <typename KeySrc>
 static __global__ __launch_bounds__(GRP_BLOCK) void k_grp_coarse(KeySrc ks, const uint32_t* __restrict__ key,
                                                                 long nidx, int ipt, uint32_t ncoarse, long nblk,
                                                                 const uint32_t* __restrict__ gscan,
-                                                                uint32_t* __restrict__ tkey,
-                                                                uint32_t* __restrict__ tval) {
+                                                                GrpRec* __restrict__ rec,
+                                                                uint32_t* __restrict__ kcount, long nbuckets) {
     extern __shared__ uint32_t cur[];
+    for (long k = blockIdx.x * long(GRP_BLOCK) + threadIdx.x; k < nbuckets; k += long(gridDim.x) * GRP_BLOCK)
+        kcount[k] = 0;
     const uint32_t blk = grp_block(nblk);
     for (uint32_t c = threadIdx.x; c < ncoarse; c += GRP_BLOCK) cur[c] = gscan[long(c) * nblk + blk];
     __syncthreads();
@@ -230,63 +258,182 @@ static __global__ __launch_bounds__(GRP_BLOCK) void k_grp_coarse(KeySrc ks, cons
             const uint32_t k = key[i];
             if (k != GRP_NONE) {
                 const uint32_t d = atomicAdd(&cur[ks.coarse(i, k)], 1u);
-                tkey[d] = k;
-                tval[d] = uint32_t(i);
+                uint32_t local;
+                double x[3];
+                ks.fetch(i, local, x);
+                u32x4* r = reinterpret_cast<u32x4*>(rec + d);
+                const unsigned long long b0x = __double_as_longlong(x[0]);
+                const unsigned long long b1x = __double_as_longlong(x[1]);
+                const unsigned long long b2x = __double_as_longlong(x[2]);
+                r[0] = u32x4{k, local, uint32_t(b0x), uint32_t(b0x >> 32)};
+                r[1] = u32x4{uint32_t(b1x), uint32_t(b1x >> 32), uint32_t(b2x), uint32_t(b2x >> 32)};
             }
         }
     }
 }
 
-template <typename Coarse, typename Src>
-static __global__ __launch_bounds__(GRP_BLOCK) void k_grp_fine(Coarse cm, Src src, const uint32_t* __restrict__ tkey,
-                                                              const uint32_t* __restrict__ tval, uint32_t nvalid,
-                                                              uint32_t ncoarse, long nblk,
-                                                              const uint32_t* __restrict__ gscan,
-                                                              uint32_t* __restrict__ hist,
-                                                              uint32_t* __restrict__ offs,
-                                                              uint32_t* __restrict__ perm,
-                                                              double* __restrict__ pos_sorted) {
+// Particles [start, end) of coarse range c in the coarse-sorted arrays.
+__device__ __forceinline__ void grp_range_span(const uint32_t* gscan, long nblk, uint32_t ncoarse, uint32_t nvalid,
+                                               uint32_t c, uint32_t& start, uint32_t& end) {
+    start = gscan[long(c) * nblk];
+    end = c + 1 < ncoarse ? gscan[long(c + 1) * nblk] : nvalid;
+}
+
+// One workgroup of GRP_PLAN_BLOCK threads: chunk lists.  cbase[c] = first
+// chunk of range c; chunk g belongs to range crange[g]; *nchunks = number of
+// chunks.  Thread t owns the ranges t*GRP_PLAN_PER .. (its range starts are
+// loaded together, then scanned over the workgroup).
+constexpr int GRP_PLAN_BLOCK = 1024;
+constexpr int GRP_PLAN_PER = int(GRP_COARSE_MAX) / GRP_PLAN_BLOCK;
+
+static __global__ __launch_bounds__(GRP_PLAN_BLOCK) void k_grp_plan(const uint32_t* __restrict__ gscan, long nblk,
+                                                                   uint32_t ncoarse, uint32_t nvalid,
+                                                                   uint32_t* __restrict__ cbase,
+                                                                   uint32_t* __restrict__ crange,
+                                                                   uint32_t* __restrict__ nchunks) {
+    __shared__ uint32_t wsum[GRP_PLAN_BLOCK / 64];
+    const uint32_t c0 = threadIdx.x * GRP_PLAN_PER;
+    uint32_t st[GRP_PLAN_PER + 1];
+#pragma unroll
+    for (int q = 0; q <= GRP_PLAN_PER; ++q) {
+        const uint32_t c = c0 + q;
+        st[q] = c < ncoarse ? gscan[long(c) * nblk] : nvalid;
+    }
+    uint32_t m[GRP_PLAN_PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < GRP_PLAN_PER; ++q) {
+        m[q] = (st[q + 1] - st[q] + GRP_CHUNK - 1) / GRP_CHUNK;
+        sum += m[q];
+    }
+    // exclusive scan of the per-thread sums: within the wavefront by shuffles,
+    // then over the wavefront totals
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    uint32_t wbase = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < GRP_PLAN_BLOCK / 64; ++w) {
+        const uint32_t v = wsum[w];
+        wbase += w < wid ? v : 0u;
+        total += v;
+    }
+    uint32_t run = wbase + incl - sum;
+#pragma unroll
+    for (int q = 0; q < GRP_PLAN_PER; ++q) {
+        const uint32_t c = c0 + q;
+        if (c < ncoarse) {
+            cbase[c] = run;
+            for (uint32_t k = 0; k < m[q]; ++k) crange[run + k] = c;
+            run += m[q];
+        }
+    }
+    if (threadIdx.x == 0) *nchunks = total;
+}
+
+// Chunk g's range, key span and particles [j0, j1); false past the last chunk.
+template <typename Coarse>
+__device__ __forceinline__ bool grp_chunk(const Coarse& cm, const uint32_t* crange, const uint32_t* cbase,
+                                          const uint32_t* nchunks, const uint32_t* gscan, long nblk,
+                                          uint32_t ncoarse, uint32_t nvalid, uint32_t g, uint32_t& klo,
+                                          uint32_t& khi, uint32_t& j0, uint32_t& j1) {
+    if (g >= __builtin_amdgcn_readfirstlane(*nchunks)) return false;
+    const uint32_t c = __builtin_amdgcn_readfirstlane(crange[g]);
+    const uint32_t q = g - __builtin_amdgcn_readfirstlane(cbase[c]);
+    uint32_t st, en;
+    grp_range_span(gscan, nblk, ncoarse, nvalid, c, st, en);
+    cm.range(c, klo, khi);
+    klo = __builtin_amdgcn_readfirstlane(klo);
+    khi = __builtin_amdgcn_readfirstlane(khi);
+    j0 = __builtin_amdgcn_readfirstlane(st) + q * GRP_CHUNK;
+    j1 = min(j0 + GRP_CHUNK, __builtin_amdgcn_readfirstlane(en));
+    return true;
+}
+
+// LDS histogram lh[0 .. khi - klo) of the keys of particles [j0, j1).
+__device__ __forceinline__ void grp_chunk_hist(const GrpRec* __restrict__ rec, uint32_t klo, uint32_t khi,
+                                               uint32_t j0, uint32_t j1, uint32_t* lh) {
+    const uint32_t nf = khi - klo;
+    for (uint32_t f = threadIdx.x; f < nf; f += GRP_BLOCK) lh[f] = 0;
+    __syncthreads();
+    for (uint32_t j = j0 + threadIdx.x; j < j1; j += GRP_BLOCK) atomicAdd(&lh[rec[j].key - klo], 1u);
+    __syncthreads();
+}
+
+template <typename Coarse>
+static __global__ __launch_bounds__(GRP_BLOCK) void k_grp_chunk_count(
+    Coarse cm, const GrpRec* __restrict__ rec, const uint32_t* __restrict__ crange,
+    const uint32_t* __restrict__ cbase, const uint32_t* __restrict__ nchunks, const uint32_t* __restrict__ gscan,
+    long nblk, uint32_t ncoarse, uint32_t nvalid, uint32_t* __restrict__ kcount) {
     extern __shared__ uint32_t lh[];
+    uint32_t klo, khi, j0, j1;
+    if (!grp_chunk(cm, crange, cbase, nchunks, gscan, nblk, ncoarse, nvalid, blockIdx.x, klo, khi, j0, j1)) return;
+    grp_chunk_hist(rec, klo, khi, j0, j1, lh);
+    for (uint32_t f = threadIdx.x; f < khi - klo; f += GRP_BLOCK)
+        if (lh[f]) atomicAdd(&kcount[klo + f], lh[f]);
+}
+
+// One workgroup per coarse range: bucket table of its keys from the counts,
+// which become the keys' cursors (first binned slot).
+template <typename Coarse>
+static __global__ __launch_bounds__(GRP_BLOCK) void k_grp_table(Coarse cm, const uint32_t* __restrict__ gscan,
+                                                               long nblk, uint32_t ncoarse, uint32_t nvalid,
+                                                               uint32_t* __restrict__ kcount,
+                                                               uint32_t* __restrict__ hist,
+                                                               uint32_t* __restrict__ offs) {
     __shared__ uint32_t sh[GRP_BLOCK];
-    const int tid = threadIdx.x;
     const uint32_t c = blockIdx.x;
-    const uint32_t start = gscan[long(c) * nblk];
-    const uint32_t end = c + 1 < ncoarse ? gscan[long(c + 1) * nblk] : nvalid;
-    uint32_t klo, khi;
+    uint32_t st, en, klo, khi;
+    grp_range_span(gscan, nblk, ncoarse, nvalid, c, st, en);
     cm.range(c, klo, khi);
     const uint32_t nf = khi - klo;
-    for (uint32_t f = tid; f < nf; f += GRP_BLOCK) lh[f] = 0;
-    __syncthreads();
-    for (uint32_t j = start + tid; j < end; j += GRP_BLOCK) atomicAdd(&lh[tkey[j] - klo], 1u);
-    __syncthreads();
-    // exclusive scan of lh[0..nf): thread t owns the segment [t*per, (t+1)*per)
+    // exclusive scan over the range's keys: thread t owns [t*per, (t+1)*per)
     const uint32_t per = (nf + GRP_BLOCK - 1) / GRP_BLOCK;
-    const uint32_t f0 = uint32_t(tid) * per;
+    const uint32_t f0 = threadIdx.x * per;
     uint32_t sum = 0;
     for (uint32_t q = 0; q < per; ++q)
-        if (f0 + q < nf) sum += lh[f0 + q];
+        if (f0 + q < nf) sum += kcount[klo + f0 + q];
     uint32_t total;
-    uint32_t run = block_exclusive_scan(sum, sh, &total) + start;
+    uint32_t run = block_exclusive_scan(sum, sh, &total) + st;
     for (uint32_t q = 0; q < per; ++q) {
         const uint32_t f = f0 + q;
         if (f < nf) {
-            const uint32_t cnt = lh[f];
+            const uint32_t cnt = kcount[klo + f];
             hist[klo + f] = cnt;
             offs[klo + f] = run;
-            lh[f] = run;
+            kcount[klo + f] = run;
             run += cnt;
         }
     }
+}
+
+template <typename Coarse>
+static __global__ __launch_bounds__(GRP_BLOCK) void k_grp_chunk_scatter(
+    Coarse cm, const GrpRec* __restrict__ rec, const uint32_t* __restrict__ crange,
+    const uint32_t* __restrict__ cbase, const uint32_t* __restrict__ nchunks, const uint32_t* __restrict__ gscan,
+    long nblk, uint32_t ncoarse, uint32_t nvalid, uint32_t* __restrict__ kcursor, uint32_t* __restrict__ perm,
+    double* __restrict__ pos_sorted) {
+    extern __shared__ uint32_t lh[];
+    uint32_t klo, khi, j0, j1;
+    if (!grp_chunk(cm, crange, cbase, nchunks, gscan, nblk, ncoarse, nvalid, blockIdx.x, klo, khi, j0, j1)) return;
+    grp_chunk_hist(rec, klo, khi, j0, j1, lh);
+    for (uint32_t f = threadIdx.x; f < khi - klo; f += GRP_BLOCK)
+        if (lh[f]) lh[f] = atomicAdd(&kcursor[klo + f], lh[f]);
     __syncthreads();
-    for (uint32_t j = start + tid; j < end; j += GRP_BLOCK) {
-        const uint32_t d = atomicAdd(&lh[tkey[j] - klo], 1u);
-        uint32_t local;
-        double x[3];
-        src.fetch(tval[j], local, x);
-        perm[d] = local;
-        pos_sorted[3 * long(d)] = x[0];
-        pos_sorted[3 * long(d) + 1] = x[1];
-        pos_sorted[3 * long(d) + 2] = x[2];
+    for (uint32_t j = j0 + threadIdx.x; j < j1; j += GRP_BLOCK) {
+        const u32x4* r = reinterpret_cast<const u32x4*>(rec + j);
+        const u32x4 a = load_global16(r), b = load_global16(r + 1);
+        const uint32_t d = atomicAdd(&lh[a.x - klo], 1u);
+        perm[d] = a.y;
+        pos_sorted[3 * long(d)] = __longlong_as_double((long long)(uint64_t(a.z) | (uint64_t(a.w) << 32)));
+        pos_sorted[3 * long(d) + 1] = __longlong_as_double((long long)(uint64_t(b.x) | (uint64_t(b.y) << 32)));
+        pos_sorted[3 * long(d) + 2] = __longlong_as_double((long long)(uint64_t(b.z) | (uint64_t(b.w) << 32)));
     }
 }
 
@@ -317,22 +464,25 @@ inline int grp_shift(uint64_t nb, long P, uint64_t target = GRP_TARGET) {
 }
 
 // Host-side plan of a grouping of `nidx` slots (nvalid of them particles)
-// over `ncoarse` coarse ranges.
+// over the keys [0, nbuckets) in `ncoarse` coarse ranges.
 struct GrpPlan {
     long nidx = 0;
     uint32_t nvalid = 0;
+    uint32_t nbuckets = 0;
     uint32_t ncoarse = 0;   // coarse ranges
     uint32_t fine_max = 0;  // most keys in one coarse range
     int ipt = 1;            // slots per thread of the coarse passes
     long nblk = 0;          // blocks of the coarse passes
     size_t ncounts = 0;     // ncoarse * nblk
     size_t nsums = 0;       // scan partial sums
+    uint32_t mmax = 0;      // most chunks of the fine passes
 };
 
-inline GrpPlan grp_plan(long nidx, uint32_t nvalid, uint32_t ncoarse, uint32_t fine_max) {
+inline GrpPlan grp_plan(long nidx, uint32_t nvalid, uint32_t nbuckets, uint32_t ncoarse, uint32_t fine_max) {
     GrpPlan g;
     g.nidx = nidx;
     g.nvalid = nvalid;
+    g.nbuckets = nbuckets;
     g.ncoarse = ncoarse > 0 ? ncoarse : 1;
     g.fine_max = fine_max;
     // at least ~512 blocks in the coarse passes, at most 32 slots per thread
@@ -343,28 +493,37 @@ inline GrpPlan grp_plan(long nidx, uint32_t nvalid, uint32_t ncoarse, uint32_t f
     if (g.nblk == 0) g.nblk = 1;
     g.ncounts = size_t(g.ncoarse) * size_t(g.nblk);
     g.nsums = (g.ncounts + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    // sum over ranges of ceil(n_c / GRP_CHUNK) <= nvalid / GRP_CHUNK + ncoarse
+    g.mmax = (nvalid + GRP_CHUNK - 1) / GRP_CHUNK + g.ncoarse;
     return g;
 }
 
-// Scratch of a grouping, in uint32 words: key (nidx), tkey and tval (nvalid
-// each), counts and their scan (ncounts each), scan sums (nsums).
+// Scratch of a grouping, in uint32 words: records (8 words per particle, at
+// the start so that they stay 16-byte aligned), key (nidx), counts and their
+// scan (ncounts each), scan sums (nsums), per-key counters (nbuckets), chunk
+// lists (ncoarse + mmax) and the chunk count.  The scratch must be 16-byte
+// aligned.
 inline size_t grp_scratch_words(const GrpPlan& g) {
-    return size_t(g.nidx) + 2 * size_t(g.nvalid) + 2 * g.ncounts + g.nsums;
+    return 8 * size_t(g.nvalid) + size_t(g.nidx) + 2 * g.ncounts + g.nsums + g.nbuckets + g.ncoarse + g.mmax + 1;
 }
 
 // Device buffers of a grouping, carved from its scratch.
 struct GrpBuffers {
-    uint32_t *key, *tkey, *tval, *counts, *gscan, *sums;
+    GrpRec* rec;
+    uint32_t *key, *counts, *gscan, *sums, *kcount, *cbase, *crange, *nchunks;
 };
 
 inline GrpBuffers grp_buffers(const GrpPlan& g, uint32_t* scratch) {
     GrpBuffers b;
-    b.key = scratch;
-    b.tkey = b.key + g.nidx;
-    b.tval = b.tkey + g.nvalid;
-    b.counts = b.tval + g.nvalid;
+    b.rec = reinterpret_cast<GrpRec*>(scratch);
+    b.key = scratch + 8 * size_t(g.nvalid);
+    b.counts = b.key + g.nidx;
     b.gscan = b.counts + g.ncounts;
     b.sums = b.gscan + g.ncounts;
+    b.kcount = b.sums + g.nsums;
+    b.cbase = b.kcount + g.nbuckets;
+    b.crange = b.cbase + g.ncoarse;
+    b.nchunks = b.crange + g.mmax;
     return b;
 }
 
@@ -384,15 +543,21 @@ inline void grp_scan(const GrpPlan& g, const GrpBuffers& b, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_apply, dim3(ns), dim3(SCAN_BLOCK), 0, st, b.counts, long(g.ncounts), b.sums, b.gscan);
 }
 
-template <typename KeySrc, typename Coarse, typename Src>
-inline void grp_scatter(const KeySrc& ks, const Coarse& cm, const Src& src, const GrpPlan& g, const GrpBuffers& b,
-                        uint32_t* hist, uint32_t* offs, uint32_t* perm, double* pos_sorted, hipStream_t st) {
+template <typename KeySrc, typename Coarse>
+inline void grp_scatter(const KeySrc& ks, const Coarse& cm, const GrpPlan& g, const GrpBuffers& b, uint32_t* hist,
+                        uint32_t* offs, uint32_t* perm, double* pos_sorted, hipStream_t st) {
+    const size_t lf = size_t(g.fine_max) * sizeof(uint32_t);
     hipLaunchKernelGGL((k_grp_coarse<KeySrc>), dim3(unsigned(g.nblk)), dim3(GRP_BLOCK),
                        size_t(g.ncoarse) * sizeof(uint32_t), st, ks, b.key, g.nidx, g.ipt, g.ncoarse, g.nblk, b.gscan,
-                       b.tkey, b.tval);
-    hipLaunchKernelGGL((k_grp_fine<Coarse, Src>), dim3(g.ncoarse), dim3(GRP_BLOCK),
-                       size_t(g.fine_max) * sizeof(uint32_t), st, cm, src, b.tkey, b.tval, g.nvalid, g.ncoarse,
-                       g.nblk, b.gscan, hist, offs, perm, pos_sorted);
+                       b.rec, b.kcount, long(g.nbuckets));
+    hipLaunchKernelGGL(k_grp_plan, dim3(1), dim3(GRP_PLAN_BLOCK), 0, st, b.gscan, g.nblk, g.ncoarse, g.nvalid,
+                       b.cbase, b.crange, b.nchunks);
+    hipLaunchKernelGGL((k_grp_chunk_count<Coarse>), dim3(g.mmax), dim3(GRP_BLOCK), lf, st, cm, b.rec, b.crange,
+                       b.cbase, b.nchunks, b.gscan, g.nblk, g.ncoarse, g.nvalid, b.kcount);
+    hipLaunchKernelGGL((k_grp_table<Coarse>), dim3(g.ncoarse), dim3(GRP_BLOCK), 0, st, cm, b.gscan, g.nblk,
+                       g.ncoarse, g.nvalid, b.kcount, hist, offs);
+    hipLaunchKernelGGL((k_grp_chunk_scatter<Coarse>), dim3(g.mmax), dim3(GRP_BLOCK), lf, st, cm, b.rec, b.crange,
+                       b.cbase, b.nchunks, b.gscan, g.nblk, g.ncoarse, g.nvalid, b.kcount, perm, pos_sorted);
 }
 
 // ----------------------------------------------------------------- gather ---
@@ -611,9 +776,6 @@ __device__ __forceinline__ void contract_and_store(const GatherArgs& a, long p, 
     store_sum<AT, C, GRAD>(a, p, lo, hi);
 }
 
-// Geometry of one LDS tile: the (T+N-1)^3 block of the ghost-padded grid that
-// holds the stencils of a T^3 tile of cells, each row of (T+N-1)*C elements
-// rounded up to whole 16-byte chunks.
 // LDS copy of the (T0+N-1) x (T1+N-1) x (T2+N-1) block of grid points that
 // the particles of a T0 x T1 x T2 cell box read: rows along axis 2, each
 // padded to whole 16-byte chunks.
@@ -636,14 +798,6 @@ struct BlockGeom {
 template <int N, typename CT, int C, int T>
 using TileGeom = BlockGeom<N, CT, C, T, T, T>;
 
-// 16 bytes as a native vector (loads and stores of it are single instructions,
-// never aggregate copies) and a load of it from global memory.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef const __attribute__((address_space(1))) u32x4 global_u32x4;
-
-__device__ __forceinline__ u32x4 load_global16(const u32x4* p) {
-    return *(global_u32x4*)p;
-}
 
 template <typename AT>
 __device__ __forceinline__ AT shfl_xor1(AT v) {
