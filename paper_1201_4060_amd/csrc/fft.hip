@@ -167,14 +167,16 @@ struct StridedCfg {
     static constexpr int THREADS = W * TEAM;
 };
 
-// Passes A and B.  Element (c, a, other, k2) of the [C][..][..][H] array sits
-// at c*sComp + a*sAxis + other*sOther + k2; the FFT runs along a.
+// Passes A and B.  Element (c, a, other, k2) of the [C][..][..][H] input sits
+// at c*sComp + a*sAxis + other*sOther + k2 (output: the same with the
+// output strides); the FFT runs along a.
 // FIRST: input is the caller's spectrum (InT pairs), multiplied by the FP64
 // symbol cAxis[a] * cOther[other] * c2[k2]; otherwise in-place on the work
 // buffer (in == out).
 template <typename T, typename InT, int LEN, bool FIRST>
 __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cplx<T>* out, int H, long sAxis,
-                                                  long sOther, long sComp, const double* cAxis,
+                                                  long sOther, long sComp, long oAxis, long oOther,
+                                                  long oComp, const double* cAxis,
                                                   const double* cOther, const double* c2,
                                                   const cplx<T>* twg) {
     using Cfg = StridedCfg<T, LEN, strided_lds_kb<LEN, FIRST>()>;
@@ -186,6 +188,7 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
     const int k2_0 = blockIdx.x * W;
     const int other = blockIdx.y;
     const long base = long(blockIdx.z) * sComp + long(other) * sOther + k2_0;
+    const long obase = long(blockIdx.z) * oComp + long(other) * oOther + k2_0;
 
     for (int i = tid; i < LEN; i += Cfg::THREADS) tw[i] = twg[i];
     // Thread tid always handles line w = tid % W; it moves PER elements of that
@@ -198,6 +201,8 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
     const bool valid = k2_0 + w < H;
     const long lane_base = base + (valid ? w : 0) + long(a0) * sAxis;
     const long step = long(RSTEP) * sAxis;
+    const long olane_base = obase + (valid ? w : 0) + long(a0) * oAxis;
+    const long ostep = long(RSTEP) * oAxis;
     cplx<T> v[PER];
     if constexpr (FIRST) {
         const double cw = (valid ? c2[k2_0 + w] : 0.0);
@@ -228,7 +233,7 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
     for (int q = 0; q < PER; ++q) v[q] = lines[w * LP + q * RSTEP + a0];
     if (valid) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) out[lane_base + q * step] = v[q];
+        for (int q = 0; q < PER; ++q) out[olane_base + q * ostep] = v[q];
     }
 }
 
@@ -265,11 +270,11 @@ struct C2rCfg {
     static constexpr int THREADS = LINES * C * TEAM;
 };
 
-// Pass C.  work[c][g0][g1][k2] (k2 <= M) -> grid[p0][p1][p2][c] with ghost
+// Pass C.  work[c][g0][g1][k2] (k2 <= M, rows of Hp) -> grid[p0][p1][p2][c] with ghost
 // planes: padded index p holds grid index (p - padlo) mod n on every axis.
 // tw[m] = exp(+2 pi i m / (2M)), m < 2M.
 template <typename T, typename OutT, int M, int C>
-__global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, OutT* __restrict__ grid,
+__global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, int Hp, OutT* __restrict__ grid,
                                              int n0, int n1, int P0, int P1, int P2, int pitch2,
                                              int padlo, const cplx<T>* __restrict__ twg) {
     using Cfg = C2rCfg<T, M, C>;
@@ -281,7 +286,7 @@ __global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, O
     const int tid = threadIdx.x;
     const long nlines = long(n0) * n1;
     const long line0 = long(blockIdx.x) * Cfg::LINES;
-    const long compStride = nlines * H;
+    const long compStride = nlines * Hp;
 
     for (int i = tid; i < 2 * M; i += Cfg::THREADS) tw[i] = twg[i];
     // load every (line, component) row of H complex values; all loads of a
@@ -295,7 +300,7 @@ __global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, O
             const int f = idx / H, k = idx - (idx / H) * H;
             const int l = f / C, c = f - (f / C) * C;
             const bool ok = idx < NL * H && line0 + l < nlines;
-            v[q] = work[ok ? long(c) * compStride + (line0 + l) * H + k : 0];
+            v[q] = work[ok ? long(c) * compStride + (line0 + l) * Hp + k : 0];
         }
 #pragma unroll
         for (int q = 0; q < ITER; ++q) {
@@ -405,7 +410,8 @@ namespace {
 
 template <typename T, typename InT, bool FIRST>
 bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, long sAxis, long sOther,
-                       long sComp, const double* cAxis, const double* cOther, const double* c2,
+                       long sComp, long oAxis, long oOther, long oComp, const double* cAxis,
+                       const double* cOther, const double* c2,
                        const cplx<T>* tw, hipStream_t s, int* Wout) {
 #define BSI_AXIS_CASE(L)                                                                           \
     case L: {                                                                                      \
@@ -413,7 +419,7 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
         *Wout = Cfg::W;                                                                            \
         grid.x = (H + Cfg::W - 1) / Cfg::W;                                                        \
         hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), grid, dim3(Cfg::THREADS), 0, s, in, out, H, sAxis, \
-                           sOther, sComp, cAxis, cOther, c2, tw);                                  \
+                           sOther, sComp, oAxis, oOther, oComp, cAxis, cOther, c2, tw);            \
         break;                                                                                     \
     }
     switch (len) {
@@ -442,14 +448,14 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
 }
 
 template <typename T, typename OutT, int C>
-bsi_status launch_c2r(int M, const cplx<T>* work, OutT* grid, int n0, int n1, int P0, int P1, int P2,
+bsi_status launch_c2r(int M, const cplx<T>* work, int Hp, OutT* grid, int n0, int n1, int P0, int P1, int P2,
                       int pitch2, int padlo, const cplx<T>* tw, hipStream_t s) {
     const long nlines = long(n0) * n1;
 #define BSI_C2R_CASE(MM)                                                                           \
     case MM: {                                                                                     \
         using Cfg = C2rCfg<T, MM, C>;                                                                 \
         const unsigned nb = unsigned((nlines + Cfg::LINES - 1) / Cfg::LINES);                      \
-        hipLaunchKernelGGL((k_c2r<T, OutT, MM, C>), dim3(nb), dim3(Cfg::THREADS), 0, s, work, grid, \
+        hipLaunchKernelGGL((k_c2r<T, OutT, MM, C>), dim3(nb), dim3(Cfg::THREADS), 0, s, work, Hp, grid, \
                            n0, n1, P0, P1, P2, pitch2, padlo, tw);                                 \
         break;                                                                                     \
     }
@@ -483,7 +489,11 @@ bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_
     bsi_ctx* ctx = f->ctx;
     const int n0 = f->n[0], n1 = f->n[1], n2 = f->n[2], C = f->C;
     const int H = n2 / 2 + 1;
-    const size_t elems = size_t(C) * n0 * n1 * H;
+    // work rows padded to whole 128-byte lines, so that the W-column row
+    // segments of the strided passes do not straddle an extra line
+    constexpr int LINE = 128 / int(sizeof(cplx<T>));
+    const int Hp = (H + LINE - 1) / LINE * LINE;
+    const size_t elems = size_t(C) * n0 * n1 * Hp;
     void* wsp = nullptr;
     BSI_TRY(get_workspace(ctx->fft_ws, s, elems * sizeof(cplx<T>), &wsp));
     cplx<T>* work = static_cast<cplx<T>*>(wsp);
@@ -496,28 +506,30 @@ bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_
     BSI_TRY(get_twiddles(ctx, n0, dbl, &tw0));
     BSI_TRY(get_twiddles(ctx, n1, dbl, &tw1));
     BSI_TRY(get_twiddles(ctx, n2, dbl, &tw2));
-    const long sComp = long(n0) * n1 * H;
+    const long sComp = long(n0) * n1 * H;    // caller's spectrum
+    const long wComp = long(n0) * n1 * Hp;   // work buffer
     int W = 0;
-    // pass A: axis 0 (stride n1*H), other = k1 (stride H)
+    // pass A: axis 0 (stride n1*H in, n1*Hp out), other = k1 (stride H in, Hp out)
     {
     StageTimer tm(ctx, "fft_axis0", s);
     BSI_TRY((launch_axis<T, InT, true>(n0, dim3(1, n1, C), uhat, work, H, long(n1) * H, long(H), sComp,
-                                       c0, c1, c2, static_cast<const cplx<T>*>(tw0), s, &W)));
+                                       long(n1) * Hp, long(Hp), wComp, c0, c1, c2,
+                                       static_cast<const cplx<T>*>(tw0), s, &W)));
     }
-    // pass B: axis 1 (stride H), other = k0 (stride n1*H), in place
+    // pass B: axis 1 (stride Hp), other = k0 (stride n1*Hp), in place
     {
     StageTimer tm(ctx, "fft_axis1", s);
     BSI_TRY((launch_axis<T, T, false>(n1, dim3(1, n0, C), reinterpret_cast<const T*>(work), work, H,
-                                      long(H), long(n1) * H, sComp, nullptr, nullptr, nullptr,
-                                      static_cast<const cplx<T>*>(tw1), s, &W)));
+                                      long(Hp), long(n1) * Hp, wComp, long(Hp), long(n1) * Hp, wComp, nullptr,
+                                      nullptr, nullptr, static_cast<const cplx<T>*>(tw1), s, &W)));
     }
     // pass C: c2r along axis 2
     const int M = n2 / 2;
     StageTimer tm(ctx, "fft_c2r", s);
     if (C == 1)
-        return launch_c2r<T, OutT, 1>(M, work, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, f->padlo,
+        return launch_c2r<T, OutT, 1>(M, work, Hp, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, f->padlo,
                                       static_cast<const cplx<T>*>(tw2), s);
-    return launch_c2r<T, OutT, 3>(M, work, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, f->padlo,
+    return launch_c2r<T, OutT, 3>(M, work, Hp, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, f->padlo,
                                   static_cast<const cplx<T>*>(tw2), s);
 }
 
