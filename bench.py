@@ -257,8 +257,18 @@ def form_plain(args):
                           "1e6 uniform particles; step = prefilter + eval per order",
               "n": N_GRID, "ncomp": NCOMP, "orders": list(ORDERS), "particles": P,
               "grid_dtype": "f32", "spectrum_dtype": "c128", "parallelism": "single GPU"}
+    # the prefilter is paid once per snapshot; per order, also the evaluation
+    # alone (binning + gather, stage times) and the prefilter alone
+    per_order = {}
+    for o in ORDERS:
+        ev = sum(stages[f"{st}@N{o}"]["avg_us"] for st in ("bin_count", "bin_scan", "bin_scatter", "gather")
+                 if f"{st}@N{o}" in stages)
+        pf = sum(stages[f"{st}@N{o}"]["avg_us"] for st in ("fft_axis0", "fft_axis1", "fft_c2r")
+                 if f"{st}@N{o}" in stages)
+        per_order[f"N{o}"] = {"eval_us": round(ev, 1), "eval_points_per_s": round(P / (ev * 1e-6), 1),
+                              "prefilter_us": round(pf, 1)}
     return base_line(args, len(ORDERS) * P / sps, "points/s", sps, "f32", config, roofline, cpu,
-                     gather_roofline=gather_rl,
+                     gather_roofline=gather_rl, per_order=per_order,
                      stages_us={k: round(v["avg_us"], 2) for k, v in stages.items()})
 
 

@@ -61,8 +61,11 @@ bsi_eval_config default_config(const bsi_field* f, int64_t P) {
                 return c;
             }
     }
-    c.sort_tile = 8;
+    // below one particle per 8^3 cells the stencils of neighbouring particles
+    // barely overlap; binning then still buys page locality on large grids,
+    // which pays for its launches only from a few 10^4 particles on
     c.variant = 1;
+    c.sort_tile = (dens >= 1.0 / 512.0 || P >= 32768) ? 8 : 0;
     return c;
 }
 
@@ -181,8 +184,8 @@ bsi_status bsi_tune(bsi_field* f, int64_t P, uint64_t seed, const char* db_path,
                 }
             }
         }
-        for (int T : {4, 8, 16, 32}) {
-            if (T < tmin) continue;
+        for (int T : {0, 4, 8, 16, 32}) {
+            if (T != 0 && T < tmin) continue;
             bsi_eval_config c{};
             c.sort_tile = T;
             c.block = 256;
