@@ -91,6 +91,44 @@ def test_gather_results_independent_of_tuning(ctx):
                 assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
 
 
+def test_gather_crowded_bucket(ctx):
+    # 1e5 particles on one point (one bucket: one coarse range cut into ~50
+    # chunks, every per-key atomic on the same key) among a few scattered
+    # ones and some non-finite ones: every configuration gives the same bits,
+    # and the crowded point matches the oracle
+    import paper_1201_4060_amd as bsi
+    from oracle import evaluate
+    grid = _grid(32, 3, 6, seed=21)
+    x0 = np.array([[1.2345, 4.5678, 0.4321]])
+    pos = np.concatenate([np.repeat(x0, 100000, axis=0), synth.uniform_positions(5000, seed=22),
+                          np.array([[np.nan, 1.0, 1.0]] * 7)])
+    perm = np.random.default_rng(23).permutation(pos.shape[0])
+    pos = pos[perm]
+    want_u, want_g = evaluate(grid, np.concatenate([x0, pos[np.isfinite(pos).all(axis=1)][:200]]), 6)
+    with bsi.Field(ctx, 32, 3, 6, bsi.BSI_F64) as f:
+        f.set_coefficients(dev(grid))
+        ref = None
+        for tile, variant, tpg in ((8, 0, 2), (4, 0, 1), (8, 1, 1), (0, 1, 1), (2, 1, 1)):
+            log(f"  crowded: tile {tile} variant {variant}")
+            before = f.nonfinite_count()
+            u, g = f.eval(dev(pos), cfg=bsi.EvalConfig(sort_tile=tile, block=256, xcd_remap=1,
+                                                       variant=variant, tiles_per_group=tpg))
+            u, g = host(u), host(g)
+            assert f.nonfinite_count() - before == 7
+            if ref is None:
+                ref = (u, g)
+                fin = np.isfinite(pos).all(axis=1)
+                assert np.isnan(u[~fin]).all() and np.isnan(g[~fin]).all()
+                crowd = np.nonzero((pos == x0).all(axis=1))[0]
+                assert crowd.size == 100000
+                assert (u[crowd] == u[crowd[0]]).all() and (g[crowd] == g[crowd[0]]).all()
+                got_u = np.concatenate([u[crowd[:1]], u[fin][:200]])
+                got_g = np.concatenate([g[crowd[:1]], g[fin][:200]])
+                assert rel_err(got_u, want_u).max() < TOL_F64
+                assert rel_err(got_g, want_g).max() < TOL_F64
+            assert np.array_equal(u, ref[0], equal_nan=True) and np.array_equal(g, ref[1], equal_nan=True)
+
+
 def test_gather_sizes_and_nonfinite(ctx):
     import torch
     import paper_1201_4060_amd as bsi
