@@ -221,7 +221,7 @@ typedef struct bsi_server_config {
     int32_t reserved[4];     /* must be 0 */
 } bsi_server_config;
 
-typedef struct bsi_server_stats {
+typedef struct bsi_server_report {
     int64_t completed;       /* requests finished successfully since the last reset      */
     int64_t failed;          /* requests that ended with an error                        */
     double p50_ns, p99_ns;   /* latency from submit to outputs in host memory            */

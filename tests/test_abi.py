@@ -44,6 +44,36 @@ def test_binding_covers_every_declared_symbol():
     assert "gfx950" in _bsi.bsi_version()
 
 
+def _struct_fields(name):
+    """Field names of `typedef struct name { ... } name;` in the header, with array sizes."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct " + name + r"\s*\{(.*?)\}\s*" + name + ";", src, flags=re.S).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = " ".join(decl.split())
+        if not decl:
+            continue
+        # "type a, b[4]": the type is everything before the first declarator
+        m = re.match(r"^((?:const\s+)?[\w*]+(?:\s*\*)*)\s+(.*)$", decl)
+        for d in m.group(2).split(","):
+            dm = re.match(r"^\**\s*(\w+)\s*(?:\[(\d+)\])?$", d.strip())
+            out.append((dm.group(1), int(dm.group(2)) if dm.group(2) else 1))
+    return out
+
+
+def test_python_structs_mirror_the_header():
+    # the ctypes mirrors must list the header's fields in the same order
+    from paper_1201_4060_amd import _bsi
+    for cname, py in (("bsi_eval_config", _bsi.EvalConfig), ("bsi_field_desc", _bsi.FieldDesc),
+                      ("bsi_server_config", _bsi.ServerConfig), ("bsi_server_report", _bsi.ServerReport),
+                      ("bsi_eval_item", _bsi.EvalItem)):
+        want = _struct_fields(cname)
+        got = []
+        for fname, ftype in py._fields_:
+            got.append((fname, getattr(ftype, "_length_", 1)))
+        assert got == want, (cname, got, want)
+
+
 def test_product_package_does_not_reference_oracle():
     pkg = os.path.join(ROOT, "paper_1201_4060_amd")
     for dirpath, _, files in os.walk(pkg):
