@@ -159,8 +159,8 @@ __device__ __forceinline__ u32x4 load_global16(const u32x4* p) {
 
 // ------------------------------------------------------- grouping by key ---
 // Particles are grouped by bucket key with a two-level counting sort that uses
-// no global atomics (their throughput, not the data volume, bounds a one-pass
-// counting sort with one atomic per particle).  The keys [0, nbuckets) are
+// no per-particle global atomics (their throughput, not the data volume, bounds
+// a one-pass counting sort with one atomic per particle).  The keys [0, nbuckets) are
 // split into `ncoarse` contiguous coarse ranges of at most GRP_FINE_MAX keys,
 // sized by the caller so that each holds a few hundred particles:
 //   k_grp_hist    each block of `ipt * GRP_BLOCK` grouping slots computes the
@@ -168,8 +168,9 @@ __device__ __forceinline__ u32x4 load_global16(const u32x4* p) {
 //                 LDS; the counts are stored range-major
 //   (scan)        exclusive scan of the counts: where each block's particles
 //                 of each coarse range go
-//   k_grp_coarse  each block scatters (key, slot) into the coarse ranges (and
-//                 clears the per-key counters of the next steps)
+//   k_grp_coarse  each block scatters its particles into the coarse ranges as
+//                 32-byte records (key, index, position), and clears the
+//                 per-key counters of the next steps
 //   k_grp_plan    one workgroup: each coarse range is cut into chunks of
 //                 GRP_CHUNK particles (a crowded range gets many), listed
 //                 range by range

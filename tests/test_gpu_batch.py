@@ -289,3 +289,69 @@ def test_tuner_roundtrip(ctx, tmp_path):
             bsi._bsi.bsi_ctx_load_tuning(ctx.handle, str(bad))
     finally:
         f.close()
+
+
+def _bench_batch_specs(count=64):
+    """The 64-field batching workload: field f has n uniform over
+    {64,128,192,256}, order uniform over {4,6} and P = round(10^U(3,6))
+    particles, drawn from stream 13 of seed 300+f (the same draws as the
+    benchmark's batching form)."""
+    from synth.rng import keyed_uniform
+    specs = []
+    for f in range(count):
+        u = keyed_uniform(300 + f, 13, np.arange(3))
+        n = (64, 128, 192, 256)[min(int(u[0] * 4), 3)]
+        N = (4, 6)[min(int(u[1] * 2), 1)]
+        specs.append((n, N, int(round(10 ** (3 + 3 * u[2])))))
+    return specs
+
+
+def test_batch_full_size_sampled():
+    # the batching workload at its full size (64 FP32 fields, 1.3e7 particles,
+    # tuned as the benchmark tunes it, graph replay): every item bitwise equal
+    # to its single-field evaluation, and a sample of every item within 1e-5
+    # of the oracle on the field's stored grid
+    import torch
+    import paper_1201_4060_amd as bsi
+    from oracle import evaluate
+    specs = _bench_batch_specs()
+    log(f"full-size batch: {len(specs)} fields, {sum(s[2] for s in specs)} particles")
+    with bsi.Context(0) as c:
+        fields, items, spec_buf = [], [], {}
+        for f, (n, N, Pf) in enumerate(specs):
+            if n not in spec_buf:
+                spec_buf[n] = torch.empty((3, n, n, n // 2 + 1), dtype=torch.complex128, device="cuda")
+            bsi._bsi.bsi_synth_kolmogorov(c.handle, n, 3, 300 + f, spec_buf[n])
+            fld = bsi.Field(c, n, 3, N, bsi.BSI_F32)
+            fld.set_spectrum(spec_buf[n])
+            pos = dev(synth.uniform_positions(Pf, seed=400 + f))
+            fields.append(fld)
+            items.append((fld, pos) + _outputs(fld, Pf))
+        del spec_buf
+        tuned = set()
+        for (n, N, Pf), fld in zip(specs, fields):
+            key = (N, round(np.log2(Pf / n ** 3)))
+            if key not in tuned:
+                tuned.add(key)
+                bsi._bsi.bsi_tune(fld.handle, Pf, seed=len(tuned))
+        try:
+            with bsi.Batch(c, items) as b:
+                for _ in range(2):
+                    b.run(use_graph=True)
+                torch.cuda.synchronize()
+                rng = np.random.default_rng(77)
+                for i, ((n, N, Pf), (fld, pos, u, g)) in enumerate(zip(specs, items)):
+                    su, sg = _single(fld, pos, b.item_config(i))
+                    torch.cuda.synchronize()
+                    assert _same(u, su) and _same(g, sg), f"item {i}"
+                    pick = rng.choice(Pf, size=min(Pf, 48), replace=False)
+                    grid = host(fld.get_coefficients())
+                    wu, wg = evaluate(grid, host(pos)[pick], N)
+                    eu = rel_err(host(u)[pick], wu).max()
+                    eg = rel_err(host(g)[pick], wg).max()
+                    assert eu < TOL_F32 and eg < TOL_F32, (i, n, N, Pf, eu, eg)
+                    del grid
+            log(f"  64 items bitwise equal to single-field runs and within {TOL_F32} of the oracle")
+        finally:
+            for fld in fields:
+                fld.close()
