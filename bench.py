@@ -99,7 +99,6 @@ def measured_traffic(key):
     known size) with a hash of the kernel's sources; the figure is returned
     only while the sources still hash the same, else None.
     """
-    import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
@@ -112,11 +111,22 @@ def measured_traffic(key):
     if ent is None:
         return None
     kind = "gather" if key.startswith("gather") else "fft"
+    return ent["traffic_bytes"] if kernel_source_hash(kind) == ent["src"] else None
+
+
+def kernel_source_hash(kind):
+    """Hash of the kernel sources of `kind` with comments and blank space
+    removed (editing a comment does not change the kernel)."""
+    import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kind]:
-        with open(os.path.join(ROOT, "paper_1201_4060_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return ent["traffic_bytes"] if h.hexdigest()[:16] == ent["src"] else None
+        with open(os.path.join(ROOT, "paper_1201_4060_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()[:16]
 
 
 def roofline_entry(key, alg, avg_us, traffic=None):
@@ -137,6 +147,9 @@ def read_stages(bsi, ctx, suffix, names=STAGES):
     return out
 
 
+STEP_PERCENTILES = {}  # ms per step of the last timed run (p10, p50, p90)
+
+
 def timed_steps(step, warmup, steps, ctxs, bsi):
     """Run warm-up steps, then time `steps` steps (synchronised on both sides)
     with per-stage kernel timing on every context; returns seconds/step."""
@@ -148,11 +161,20 @@ def timed_steps(step, warmup, steps, ctxs, bsi):
         bsi._bsi.bsi_ctx_reset_timing(c.handle)
         bsi._bsi.bsi_ctx_set_timing(c.handle, True)
     torch.cuda.synchronize()
+    # an event after every step on torch's stream (the library works on it):
+    # per-step durations for the percentiles, the wall clock for the mean
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for i in range(steps):
         step()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    STEP_PERCENTILES.update({"p10": round(float(np.percentile(per, 10)), 4),
+                             "p50": round(float(np.percentile(per, 50)), 4),
+                             "p90": round(float(np.percentile(per, 90)), 4)})
     return (t1 - t0) / steps
 
 
@@ -179,6 +201,8 @@ def base_line(args, value, unit, sec_per_step, dtype, config, roofline, cpu, **e
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec_per_step * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
             "data": "synthetic", "config": config, "roofline": roofline}
+    if STEP_PERCENTILES:
+        line["ms_per_step_percentiles"] = dict(STEP_PERCENTILES)
     line.update(extra)
     line["cpu_baseline"] = cpu
     return line
@@ -476,6 +500,7 @@ def form_batch(args):
     n_tiled = sum(1 for c in modes if c.variant == 0)
 
     sps = timed_steps(lambda: batch.run(use_graph=True), args.warmup, args.steps, [ctx], bsi)
+    graph_pct = dict(STEP_PERCENTILES)
     graph = read_stages(bsi, ctx, "graph", ("batch_graph",))
     # the same batch enqueued directly, for the per-kernel times
     sps_eager = timed_steps(lambda: batch.run(use_graph=False), 1, args.steps, [ctx], bsi)
@@ -530,6 +555,8 @@ def form_batch(args):
                           "replay of the captured graph (binning + one persistent gather launch)",
               "fields": len(specs), "particles": Ptot, "tiled_items": n_tiled,
               "direct_items": len(specs) - n_tiled, "tuning_runs": len(tuned), "parallelism": "single GPU"}
+    STEP_PERCENTILES.clear()
+    STEP_PERCENTILES.update(graph_pct)   # the step the line reports: the graph replay
     return base_line(args, Ptot / sps, "points/s", sps, "f32", config, roofline, cpu,
                      direct_enqueue_points_per_s=round(Ptot / sps_eager, 1),
                      per_field_launches_points_per_s=round(Ptot / sps_single, 1),
