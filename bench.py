@@ -150,16 +150,18 @@ def read_stages(bsi, ctx, suffix, names=STAGES):
 STEP_PERCENTILES = {}  # ms per step of the last timed run (p10, p50, p90)
 
 
-def timed_steps(step, warmup, steps, ctxs, bsi):
-    """Run warm-up steps, then time `steps` steps (synchronised on both sides)
-    with per-stage kernel timing on every context; returns seconds/step."""
+def timed_steps(step, warmup, steps, ctxs, bsi, stage_timing=True):
+    """Run warm-up steps, then time `steps` steps (synchronised on both sides),
+    with the library's per-stage kernel timing on every context if
+    `stage_timing` (its events cost several % of a step: the figure a line
+    reports comes from a run without them); returns seconds/step."""
     import torch
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     for c in ctxs:
         bsi._bsi.bsi_ctx_reset_timing(c.handle)
-        bsi._bsi.bsi_ctx_set_timing(c.handle, True)
+        bsi._bsi.bsi_ctx_set_timing(c.handle, stage_timing)
     torch.cuda.synchronize()
     # an event after every step on torch's stream (the library works on it):
     # per-step durations for the percentiles, the wall clock for the mean
@@ -264,12 +266,18 @@ def form_plain(args):
             fields[o].set_spectrum(uhat)
             fields[o].eval(pos, cfg=cfg, out=outs[o])
 
-    sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi)
+    sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi, stage_timing=False)
+    pct = dict(STEP_PERCENTILES)
+    # the same steps again with the library's stage events, for the kernel times
+    sps_inst = timed_steps(step, 1, args.steps, list(ctxs.values()), bsi)
+    STEP_PERCENTILES.clear()
+    STEP_PERCENTILES.update(pct)
     stages = {}
     for o in ORDERS:
         stages.update(read_stages(bsi, ctxs[o], f"N{o}"))
         bsi._bsi.bsi_ctx_set_timing(ctxs[o].handle, False)
-    print_stages(stages, sps, args.steps)
+    eprint(f"{sps * 1e3:.3f} ms/step without stage events, {sps_inst * 1e3:.3f} ms/step with them")
+    print_stages(stages, sps_inst, args.steps)
 
     # cold last-level cache: the 201 MB grid fits the 256 MB Infinity Cache,
     # so the gather is also timed with a 512 MB buffer written before each call
@@ -371,12 +379,17 @@ def form_precision(args):
             fields[k].set_spectrum(uhat)
             fields[k].eval(pos, out=outs[k])
 
-    sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi)
+    sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi, stage_timing=False)
+    pct = dict(STEP_PERCENTILES)
+    sps_inst = timed_steps(step, 1, args.steps, list(ctxs.values()), bsi)
+    STEP_PERCENTILES.clear()
+    STEP_PERCENTILES.update(pct)
+    eprint(f"{sps * 1e3:.3f} ms/step without stage events, {sps_inst * 1e3:.3f} ms/step with them")
     stages = {}
     for k, _, _ in kinds:
         stages.update(read_stages(bsi, ctxs[k], k))
         bsi._bsi.bsi_ctx_set_timing(ctxs[k].handle, False)
-    print_stages(stages, sps, args.steps)
+    print_stages(stages, sps_inst, args.steps)
     U = distinct_stencil_points(pos, n, N)
     cbytes = {k: cb for k, _, cb in kinds}
     alg = {}
@@ -499,8 +512,11 @@ def form_batch(args):
     modes = [batch.item_config(i) for i in range(len(items))]
     n_tiled = sum(1 for c in modes if c.variant == 0)
 
-    sps = timed_steps(lambda: batch.run(use_graph=True), args.warmup, args.steps, [ctx], bsi)
+    # the figure of the line: graph replays without the library's stage events
+    sps = timed_steps(lambda: batch.run(use_graph=True), args.warmup, args.steps, [ctx], bsi,
+                      stage_timing=False)
     graph_pct = dict(STEP_PERCENTILES)
+    timed_steps(lambda: batch.run(use_graph=True), 1, args.steps, [ctx], bsi)
     graph = read_stages(bsi, ctx, "graph", ("batch_graph",))
     # the same batch enqueued directly, for the per-kernel times
     sps_eager = timed_steps(lambda: batch.run(use_graph=False), 1, args.steps, [ctx], bsi)
@@ -513,7 +529,8 @@ def form_batch(args):
         for (fl, pos, u, g), c in zip(items, cfgs):
             fl.eval(pos, cfg=c, out=(u, g))
 
-    sps_single = timed_steps(singles, 1, args.steps, [ctx], bsi)
+    sps_single = timed_steps(singles, 1, args.steps, [ctx], bsi, stage_timing=False)
+    timed_steps(singles, 1, args.steps, [ctx], bsi)
     st_single = read_stages(bsi, ctx, "single", ("gather",))
     bsi._bsi.bsi_ctx_set_timing(ctx.handle, False)
     stages = {**graph, **st_eager, **st_single}
