@@ -33,6 +33,11 @@ template <int LEN, bool FIRST>
 constexpr int strided_lds_kb() {
     return (FIRST && LEN >= 512) ? BSI_FFT_LDS_KB_LONG_FIRST : BSI_FFT_LDS_KB;
 }
+// XCD-contiguous block order (k_fft_axis): the first pass with two blocks per CU
+template <int LEN, bool FIRST>
+constexpr bool fft_remap() {
+    return FIRST && strided_lds_kb<LEN, FIRST>() == BSI_FFT_LDS_KB;
+}
 
 namespace bsi {
 
@@ -174,8 +179,8 @@ struct StridedCfg {
 // symbol cAxis[a] * cOther[other] * c2[k2]; otherwise in-place on the work
 // buffer (in == out).
 template <typename T, typename InT, int LEN, bool FIRST>
-__global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cplx<T>* out, int H, long sAxis,
-                                                  long sOther, long sComp, long oAxis, long oOther,
+__global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cplx<T>* out, int H, int gx, int gy,
+                                                  long sAxis, long sOther, long sComp, long oAxis, long oOther,
                                                   long oComp, const double* cAxis,
                                                   const double* cOther, const double* c2,
                                                   const cplx<T>* twg) {
@@ -185,10 +190,29 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
     __shared__ cplx<T> lines[W * LP];
     __shared__ cplx<T> tw[LEN];
     const int tid = threadIdx.x;
-    const int k2_0 = blockIdx.x * W;
-    const int other = blockIdx.y;
-    const long base = long(blockIdx.z) * sComp + long(other) * sOther + k2_0;
-    const long obase = long(blockIdx.z) * oComp + long(other) * oOther + k2_0;
+    // Block (column block bx, row set `other`, component bz).  Workgroups are
+    // dispatched round-robin over the 8 XCDs; in the first pass with two
+    // blocks per CU the grid is one-dimensional and each XCD is given one
+    // contiguous range of logical blocks instead, so that the column blocks of
+    // one row set run on one XCD and the cache lines they share in the
+    // caller's (unaligned) rows are L2 hits.  Elsewhere the plain
+    // three-dimensional grid measured as fast or faster.
+    int bx, other, bz;
+    if constexpr (fft_remap<LEN, FIRST>()) {
+        const long nblocks = gridDim.x;
+        const long q8 = nblocks / 8, r8 = nblocks % 8, x8 = blockIdx.x % 8;
+        const long lb = x8 * q8 + (x8 < r8 ? x8 : r8) + blockIdx.x / 8;
+        bx = int(lb % gx);
+        other = int((lb / gx) % gy);
+        bz = int(lb / (long(gx) * gy));
+    } else {
+        bx = blockIdx.x;
+        other = blockIdx.y;
+        bz = blockIdx.z;
+    }
+    const int k2_0 = bx * W;
+    const long base = long(bz) * sComp + long(other) * sOther + k2_0;
+    const long obase = long(bz) * oComp + long(other) * oOther + k2_0;
 
     for (int i = tid; i < LEN; i += Cfg::THREADS) tw[i] = twg[i];
     // Thread tid always handles line w = tid % W; it moves PER elements of that
@@ -417,9 +441,11 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
     case L: {                                                                                      \
         using Cfg = StridedCfg<T, L, strided_lds_kb<L, FIRST>()>;                                  \
         *Wout = Cfg::W;                                                                            \
-        grid.x = (H + Cfg::W - 1) / Cfg::W;                                                        \
-        hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), grid, dim3(Cfg::THREADS), 0, s, in, out, H, sAxis, \
-                           sOther, sComp, oAxis, oOther, oComp, cAxis, cOther, c2, tw);            \
+        const int gx = (H + Cfg::W - 1) / Cfg::W;                                                  \
+        const dim3 g = fft_remap<L, FIRST>() ? dim3(unsigned(gx) * grid.y * grid.z)              \
+                                              : dim3(unsigned(gx), grid.y, grid.z);              \
+        hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), g, dim3(Cfg::THREADS), 0, s, in, out, H, gx, \
+                           int(grid.y), sAxis, sOther, sComp, oAxis, oOther, oComp, cAxis, cOther, c2, tw); \
         break;                                                                                     \
     }
     switch (len) {
