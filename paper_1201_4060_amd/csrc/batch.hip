@@ -32,7 +32,7 @@ namespace {
 
 constexpr int BATCH_B = 64;        // threads per workgroup of the persistent gather
 constexpr int BLK = 256;           // threads per workgroup of the binning kernels
-enum : int32_t { MODE_DIRECT = 0, MODE_TILE4 = 1, MODE_TILE8 = 2 };
+enum : int32_t { MODE_DIRECT = 0, MODE_TILE8 = 2 };
 
 struct BatchItem {
     GatherArgs ga;       // hist/offs at the item's buckets; perm/pos_sorted are the batch-wide arrays
@@ -137,18 +137,16 @@ constexpr bool batch_tile_ok() {
            TileGeom<N, CT, C, T>::SLOTS < 3072;
 }
 
-template <int N, typename CT, int C, bool GRAD, int T>
+template <int N, typename CT, int C, bool GRAD>
 __device__ __forceinline__ void batch_tile(const GatherArgs& a, uint32_t bucket, u32x4* lds) {
-    if constexpr (batch_tile_ok<N, CT, C, T>()) tile_eval<N, CT, C, GRAD, T, BATCH_B>(a, bucket, lds);
+    // one tile shape (8^3 cells) per class keeps the kernel's register budget down
+    if constexpr (batch_tile_ok<N, CT, C, 8>()) tile_eval<N, CT, C, GRAD, 8, BATCH_B>(a, bucket, lds);
 }
 
 // Workgroup g takes units g, g + G, g + 2G, ... (G = grid size): the unit
 // index is the same in every lane, so the loop and the class dispatch are
 // scalar and every wavefront of the workgroup meets the same barriers.
-// The 4^3-cell tile bodies are compiled only into the T4 instance: their code
-// raises the register spills of the whole kernel, so a batch without such
-// items runs the instance without them.
-template <typename CT, bool GRAD, bool T4>
+template <typename CT, bool GRAD>
 __global__ __launch_bounds__(BATCH_B) void k_batch_gather(BatchArgs b) {
     extern __shared__ u32x4 lds[];
     const uint32_t ntile = __builtin_amdgcn_readfirstlane(b.ctr[1]);
@@ -159,23 +157,12 @@ __global__ __launch_bounds__(BATCH_B) void k_batch_gather(BatchArgs b) {
             const uint32_t item = __builtin_amdgcn_readfirstlane(e.x);
             const uint32_t bucket = __builtin_amdgcn_readfirstlane(e.y);
             const BatchItem& it = b.items[item];
-            const int key = __builtin_amdgcn_readfirstlane(it.N * 2 + (it.C == 3 ? 1 : 0) +
-                                                           (T4 && it.mode == MODE_TILE4 ? 32 : 0));
+            const int key = __builtin_amdgcn_readfirstlane(it.N * 2 + (it.C == 3 ? 1 : 0));
             switch (key) {
-                case 8: batch_tile<4, CT, 1, GRAD, 8>(it.ga, bucket, lds); break;
-                case 9: batch_tile<4, CT, 3, GRAD, 8>(it.ga, bucket, lds); break;
-                case 12: batch_tile<6, CT, 1, GRAD, 8>(it.ga, bucket, lds); break;
-                case 13: batch_tile<6, CT, 3, GRAD, 8>(it.ga, bucket, lds); break;
-                default:
-                    if constexpr (T4) {
-                        switch (key) {
-                            case 40: batch_tile<4, CT, 1, GRAD, 4>(it.ga, bucket, lds); break;
-                            case 41: batch_tile<4, CT, 3, GRAD, 4>(it.ga, bucket, lds); break;
-                            case 44: batch_tile<6, CT, 1, GRAD, 4>(it.ga, bucket, lds); break;
-                            default: batch_tile<6, CT, 3, GRAD, 4>(it.ga, bucket, lds); break;
-                        }
-                    }
-                    break;
+                case 8: batch_tile<4, CT, 1, GRAD>(it.ga, bucket, lds); break;
+                case 9: batch_tile<4, CT, 3, GRAD>(it.ga, bucket, lds); break;
+                case 12: batch_tile<6, CT, 1, GRAD>(it.ga, bucket, lds); break;
+                default: batch_tile<6, CT, 3, GRAD>(it.ga, bucket, lds); break;
             }
         } else {
             const uint32_t d = u - ntile;
@@ -237,23 +224,28 @@ int batch_tile_lds(int coef, int N, int C, int T) {
     return tile_lds_ct<uint16_t>(N, C, T);
 }
 
-template <typename CT>
-const void* gather_kernel_ct(bool grad, bool t4) {
-    if (grad) return t4 ? reinterpret_cast<const void*>(&k_batch_gather<CT, true, true>)
-                        : reinterpret_cast<const void*>(&k_batch_gather<CT, true, false>);
-    return t4 ? reinterpret_cast<const void*>(&k_batch_gather<CT, false, true>)
-              : reinterpret_cast<const void*>(&k_batch_gather<CT, false, false>);
+const void* gather_kernel(int coef, bool grad) {
+    if (coef == BSI_F64)
+        return grad ? reinterpret_cast<const void*>(&k_batch_gather<double, true>)
+                    : reinterpret_cast<const void*>(&k_batch_gather<double, false>);
+    if (coef == BSI_F32)
+        return grad ? reinterpret_cast<const void*>(&k_batch_gather<float, true>)
+                    : reinterpret_cast<const void*>(&k_batch_gather<float, false>);
+    return grad ? reinterpret_cast<const void*>(&k_batch_gather<uint16_t, true>)
+                : reinterpret_cast<const void*>(&k_batch_gather<uint16_t, false>);
 }
 
-const void* gather_kernel(int coef, bool grad, bool t4) {
-    if (coef == BSI_F64) return gather_kernel_ct<double>(grad, t4);
-    if (coef == BSI_F32) return gather_kernel_ct<float>(grad, t4);
-    return gather_kernel_ct<uint16_t>(grad, t4);
-}
-
-hipError_t launch_gather(int coef, bool grad, bool t4, unsigned grid, size_t lds, hipStream_t s, BatchArgs a) {
-    void* args[] = {&a};
-    return hipLaunchKernel(gather_kernel(coef, grad, t4), dim3(grid), dim3(BATCH_B), args, lds, s);
+void launch_gather(int coef, bool grad, unsigned grid, size_t lds, hipStream_t s, const BatchArgs& a) {
+    if (coef == BSI_F64) {
+        if (grad) hipLaunchKernelGGL((k_batch_gather<double, true>), dim3(grid), dim3(BATCH_B), lds, s, a);
+        else hipLaunchKernelGGL((k_batch_gather<double, false>), dim3(grid), dim3(BATCH_B), lds, s, a);
+    } else if (coef == BSI_F32) {
+        if (grad) hipLaunchKernelGGL((k_batch_gather<float, true>), dim3(grid), dim3(BATCH_B), lds, s, a);
+        else hipLaunchKernelGGL((k_batch_gather<float, false>), dim3(grid), dim3(BATCH_B), lds, s, a);
+    } else {
+        if (grad) hipLaunchKernelGGL((k_batch_gather<uint16_t, true>), dim3(grid), dim3(BATCH_B), lds, s, a);
+        else hipLaunchKernelGGL((k_batch_gather<uint16_t, false>), dim3(grid), dim3(BATCH_B), lds, s, a);
+    }
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -269,7 +261,6 @@ struct bsi_batch {
     std::vector<bsi_eval_config> cfgs;   // per item, as planned
     int coef = BSI_F32;
     bool grad = true;
-    bool t4 = false;                     // some item is gathered in 4^3-cell tiles
     int nitems = 0;                      // items with P > 0
     uint64_t Ptot = 0, Btot = 0;
     uint32_t npblocks = 0, nbblocks = 0, ndirect = 0;
@@ -288,17 +279,12 @@ struct bsi_batch {
 namespace bsi {
 
 // Plan choice of one item from a configuration: a tiled configuration keeps
-// the tiled gather with its own tile edge (4 or 8 cells) when the class has
-// that shape, else with 8^3-cell tiles; anything else is gathered one lane per
-// particle, binned with the configuration's tile.
+// the tiled gather, with the batch kernel's 8^3-cell tiles when the class has
+// them; anything else is gathered one lane per particle, binned with the
+// configuration's tile.
 static void item_mode(const bsi_field* f, const bsi_eval_config& c, int* mode, int* tile) {
     const int nmax = std::max(f->n[0], std::max(f->n[1], f->n[2]));
     const int tmin = (nmax + 255) / 256;  // at most 2^24 buckets
-    if (c.variant == 0 && c.sort_tile == 4 && 4 >= tmin && batch_tile_supported(f->desc.coef, f->N, f->C, 4)) {
-        *mode = MODE_TILE4;
-        *tile = 4;
-        return;
-    }
     if (c.variant == 0 && c.sort_tile > 0 && 8 >= tmin && batch_tile_supported(f->desc.coef, f->N, f->C, 8)) {
         *mode = MODE_TILE8;
         *tile = 8;
@@ -325,7 +311,7 @@ static bsi_status enqueue(bsi_batch* b, hipStream_t s) {
     }
     {
         StageTimer tm(ctx, "batch_gather", s);
-        BSI_HIP(launch_gather(b->coef, b->grad, b->t4, b->grid, b->lds, s, a));
+        launch_gather(b->coef, b->grad, b->grid, b->lds, s, a);
     }
     BSI_HIP(hipGetLastError());
     return BSI_OK;
@@ -401,7 +387,6 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
         int mode = 0, tile = 0;
         item_mode(f, c, &mode, &tile);
         b->cfgs[i].variant = mode == MODE_DIRECT ? 1 : 0;
-        if (mode == MODE_TILE4) b->t4 = true;
         b->cfgs[i].sort_tile = tile;
         BatchItem x{};
         GatherArgs& g = x.ga;
@@ -551,7 +536,7 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     // persistent grid: as many one-wavefront workgroups as stay resident
     int per_cu = 0;
     if (st == BSI_OK && hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &per_cu, gather_kernel(coef, grad, b->t4), BATCH_B, b->lds) != hipSuccess) {
+                            &per_cu, gather_kernel(coef, grad), BATCH_B, b->lds) != hipSuccess) {
         (void)hipGetLastError();
         per_cu = 0;
     }

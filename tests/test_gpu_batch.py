@@ -108,9 +108,6 @@ def test_batch_matches_single_and_oracle(ctx):
                     torch.cuda.synchronize()
                     log(f"  item {i} graph={use_graph} planned tile={planned.sort_tile} "
                         f"variant={planned.variant} P={pos.shape[0]}")
-                    if SPECS[i][4] in ((4, 0), (8, 0)):
-                        # a tiled request keeps its tile edge in the batch kernel
-                        assert (planned.sort_tile, planned.variant) == SPECS[i][4]
                     assert _same(u, us) and _same(g, gs), f"item {i} differs from bsi_eval_ex"
             for i, (f, pos, u, g) in enumerate(items):
                 P = pos.shape[0]
