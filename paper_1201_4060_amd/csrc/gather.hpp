@@ -880,10 +880,12 @@ __device__ __forceinline__ void direct_eval(const GatherArgs& a, long j, bool st
     }
 }
 
-// LDS bytes one workgroup of B threads needs for the block geometry G.
+// LDS bytes one workgroup of B threads needs for the block geometry G: the
+// block itself (lanes past its last slot load nothing), so that as many blocks
+// as possible fit a CU (six of 27 KB for order 6 with 8^3 tiles).
 template <typename G, int B>
 constexpr int block_lds_bytes() {
-    return (G::SLOTS + B - 1) / B * B * 16;
+    return G::SLOTS * 16;
 }
 
 template <int N, typename CT, int C, int T, int B>
@@ -946,10 +948,13 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
             const int ch = sl - row * G::CH;
             const int r0 = row / G::R1;
             const int r1 = row - r0 * G::R1;
-            const bool ok = sl < G::SLOTS && r0 < tl.lim0 && r1 < tl.lim1;
-            __builtin_amdgcn_global_load_lds((global_u32x4*)(tl.g + (ok ? r0 * tl.p0v + r1 * tl.p1v + ch : 0)),
-                                             (__attribute__((address_space(3))) void*)(lds + q * B + wbase),
-                                             16, 0, 0);
+            const bool ok = r0 < tl.lim0 && r1 < tl.lim1;
+            // only the last step can reach past the block; its lanes there
+            // are masked off and write no LDS
+            if (q < PERB - 1 || sl < G::SLOTS)
+                __builtin_amdgcn_global_load_lds(
+                    (global_u32x4*)(tl.g + (ok ? r0 * tl.p0v + r1 * tl.p1v + ch : 0)),
+                    (__attribute__((address_space(3))) void*)(lds + q * B + wbase), 16, 0, 0);
         }
         // the weights' arithmetic stays below every block load: the compiler
         // waits for all loads in flight before the first use of a position,
