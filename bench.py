@@ -180,6 +180,22 @@ def timed_steps(step, warmup, steps, ctxs, bsi, stage_timing=True):
     return (t1 - t0) / steps
 
 
+def overlapped(parts, sides):
+    """Run the independent parts of a step concurrently: parts[0] on torch's
+    current stream, parts[i] on sides[i - 1] (default priority), all joined
+    back into the current stream at the end."""
+    import torch
+    main = torch.cuda.current_stream()
+    for s in sides:
+        s.wait_stream(main)
+    for part, s in zip(parts[1:], sides):
+        with torch.cuda.stream(s):
+            part()
+    parts[0]()
+    for s in sides:
+        main.wait_stream(s)
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=10):
     """GB/s (bytes read + written) of a plain 1 GiB device-to-device copy: the
     practical yardstick beside the 8 TB/s datasheet peak."""
@@ -261,22 +277,42 @@ def form_plain(args):
     if args.sort_tile is not None:
         cfg = bsi.EvalConfig(sort_tile=args.sort_tile, block=256, xcd_remap=1)
 
-    def step():
-        for o in ORDERS:
+    def order_part(o):
+        def run():
             fields[o].set_spectrum(uhat)
             fields[o].eval(pos, cfg=cfg, out=outs[o])
+        return run
+
+    def step_one_stream():
+        for o in ORDERS:
+            order_part(o)()
+
+    # the two orders are independent: with --streams 2 they run on two streams,
+    # so that one order's memory-bound FFT passes overlap the other's gather
+    sides = [torch.cuda.Stream() for _ in ORDERS[1:]]
+    parts = [order_part(o) for o in ORDERS]
+
+    def step():
+        if args.streams > 1:
+            overlapped(parts, sides)
+        else:
+            step_one_stream()
 
     sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi, stage_timing=False)
     pct = dict(STEP_PERCENTILES)
-    # the same steps again with the library's stage events, for the kernel times
-    sps_inst = timed_steps(step, 1, args.steps, list(ctxs.values()), bsi)
+    sps_one = sps if args.streams == 1 else timed_steps(step_one_stream, 1, args.steps, list(ctxs.values()),
+                                                         bsi, stage_timing=False)
+    # the same steps again on one stream with the library's stage events, so
+    # that every kernel is timed alone
+    sps_inst = timed_steps(step_one_stream, 1, args.steps, list(ctxs.values()), bsi)
     STEP_PERCENTILES.clear()
     STEP_PERCENTILES.update(pct)
     stages = {}
     for o in ORDERS:
         stages.update(read_stages(bsi, ctxs[o], f"N{o}"))
         bsi._bsi.bsi_ctx_set_timing(ctxs[o].handle, False)
-    eprint(f"{sps * 1e3:.3f} ms/step without stage events, {sps_inst * 1e3:.3f} ms/step with them")
+    eprint(f"{sps * 1e3:.3f} ms/step on {args.streams} stream(s), {sps_one * 1e3:.3f} on one stream, "
+           f"{sps_inst * 1e3:.3f} on one stream with stage events")
     print_stages(stages, sps_inst, args.steps)
 
     # cold last-level cache: the 201 MB grid fits the 256 MB Infinity Cache,
@@ -346,6 +382,7 @@ def form_plain(args):
         per_order[f"N{o}"] = {"eval_us": round(ev, 1), "eval_points_per_s": round(P / (ev * 1e-6), 1),
                               "prefilter_us": round(pf, 1)}
     return base_line(args, len(ORDERS) * P / sps, "points/s", sps, "f32", config, roofline, cpu,
+                     streams=args.streams, ms_per_step_one_stream=round(sps_one * 1e3, 4),
                      gather_roofline=gather_rl, fft_roofline=fft_rl, per_order=per_order,
                      copy_GBs=round(copy_gbs, 1),
                      stages_us={k: round(v["avg_us"], 2) for k, v in stages.items()})
@@ -374,17 +411,35 @@ def form_precision(args):
     outs = {k: (torch.empty((Pp, C), dtype=torch.float32, device=dev),
                 torch.empty((Pp, C, 3), dtype=torch.float32, device=dev)) for k, _, _ in kinds}
 
-    def step():
-        for k, _, _ in kinds:
+    def kind_part(k):
+        def run():
             fields[k].set_spectrum(uhat)
             fields[k].eval(pos, out=outs[k])
+        return run
+
+    def step_one_stream():
+        for k, _, _ in kinds:
+            kind_part(k)()
+
+    # the two grid types are independent: with --streams 2 they run on two streams
+    sides = [torch.cuda.Stream() for _ in kinds[1:]]
+    parts = [kind_part(k) for k, _, _ in kinds]
+
+    def step():
+        if args.streams > 1:
+            overlapped(parts, sides)
+        else:
+            step_one_stream()
 
     sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi, stage_timing=False)
     pct = dict(STEP_PERCENTILES)
-    sps_inst = timed_steps(step, 1, args.steps, list(ctxs.values()), bsi)
+    sps_one = sps if args.streams == 1 else timed_steps(step_one_stream, 1, args.steps, list(ctxs.values()),
+                                                         bsi, stage_timing=False)
+    sps_inst = timed_steps(step_one_stream, 1, args.steps, list(ctxs.values()), bsi)
     STEP_PERCENTILES.clear()
     STEP_PERCENTILES.update(pct)
-    eprint(f"{sps * 1e3:.3f} ms/step without stage events, {sps_inst * 1e3:.3f} ms/step with them")
+    eprint(f"{sps * 1e3:.3f} ms/step on {args.streams} stream(s), {sps_one * 1e3:.3f} on one stream, "
+           f"{sps_inst * 1e3:.3f} on one stream with stage events")
     stages = {}
     for k, _, _ in kinds:
         stages.update(read_stages(bsi, ctxs[k], k))
@@ -454,6 +509,7 @@ def form_precision(args):
               "n": n, "ncomp": C, "order": N, "particles": Pp, "grid_dtypes": ["f32", "bf16"],
               "parallelism": "single GPU"}
     return base_line(args, 2 * Pp / sps, "points/s", sps, "f32", config, roofline, cpu, per_grid_dtype=per,
+                     streams=args.streams, ms_per_step_one_stream=round(sps_one * 1e3, 4),
                      stages_us={k: round(v["avg_us"], 2) for k, v in stages.items()})
 
 
@@ -734,6 +790,8 @@ def main():
     ap.add_argument("--cpu-sample-precision", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort-tile", type=int, default=None)
+    ap.add_argument("--streams", type=int, choices=(1, 2), default=2,
+                    help="plain and precision forms: run the two independent halves of a step on 1 or 2 streams")
     ap.add_argument("--serve-scale", choices=("full", "small"), default="full")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=8)
