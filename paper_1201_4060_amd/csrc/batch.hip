@@ -331,7 +331,7 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     const bsi_field* f0 = items[0].field;
     BSI_CHECK(f0 != nullptr, BSI_E_INVAL, "item 0 has no field");
     const int coef = f0->desc.coef;
-    // grad presence is judged on the items with particles (empty tensors may
+    // grad presence is decided on the items with particles (empty tensors may
     // come with NULL pointers)
     bool grad = items[0].grad != nullptr;
     for (int i = 0; i < count; ++i)
