@@ -162,6 +162,23 @@ bsi_status bsi_eval_ex(bsi_field* field, const double* pos_dev, int64_t P,
 bsi_status bsi_debug_cells(bsi_field* field, const double* pos_dev, int64_t P,
                            int32_t* cell_dev, double* t_dev, void* hip_stream);
 
+/* The binning of the evaluation path, for tests (not part of the method: a
+ * locality device).  Buckets are Morton tiles of `tile` cells per edge (tile
+ * >= 1 and >= ceil(max(n) / 256), else BSI_E_INVAL): bucket b < nbuckets - 1
+ * holds the particles whose cell (bsi_debug_cells) lies in the tile with
+ * coordinates (cell_d / tile) whose bits interleave into b, axis 0 highest of
+ * each triple; the last bucket holds the particles without a cell.  Always sets
+ * *nbuckets (> 0).  With hist_dev == NULL nothing else is done; otherwise
+ * hist_dev and offs_dev (device uint32 [nbuckets]) receive each bucket's
+ * particle count and first binned slot (the exclusive prefix sum of the
+ * counts), perm_dev (device uint32 [P]) the particle index held by every binned
+ * slot and pos_sorted_dev (device FP64 [P][3]) its position.  The order of the
+ * particles inside a bucket is unspecified.  Uses the context's evaluation
+ * workspace of the stream. */
+bsi_status bsi_debug_bins(bsi_field* field, const double* pos_dev, int64_t P, int32_t tile,
+                          uint32_t* hist_dev, uint32_t* offs_dev, uint32_t* perm_dev,
+                          double* pos_sorted_dev, int64_t* nbuckets, void* hip_stream);
+
 /* Number of non-finite positions seen by evaluations of this field so far
  * (synchronises the field's last stream). */
 bsi_status bsi_field_stats(bsi_field* field, int64_t* nonfinite_positions);

@@ -90,6 +90,7 @@ SIGNATURES = {
     "bsi_eval": (ST, [VP, VP, I64, VP, VP, VP]),
     "bsi_eval_ex": (ST, [VP, VP, I64, VP, VP, ctypes.POINTER(EvalConfig), VP]),
     "bsi_debug_cells": (ST, [VP, VP, I64, VP, VP, VP]),
+    "bsi_debug_bins": (ST, [VP, VP, I64, I32, VP, VP, VP, VP, ctypes.POINTER(I64), VP]),
     "bsi_field_stats": (ST, [VP, ctypes.POINTER(I64)]),
     "bsi_ctx_set_timing": (ST, [VP, I32]),
     "bsi_ctx_read_timing": (ST, [VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -219,6 +220,14 @@ def bsi_eval_ex(field, pos, P, u, grad=None, cfg=None, stream=None):
 
 def bsi_debug_cells(field, pos, P, cell, t, stream=None):
     _check(lib().bsi_debug_cells(field, _ptr(pos), P, _ptr(cell), _ptr(t), stream), "bsi_debug_cells")
+
+
+def bsi_debug_bins(field, pos, P, tile, hist, offs, perm, pos_sorted, stream=None):
+    """Returns the bucket count; fills the four arrays unless hist is None."""
+    n = I64()
+    _check(lib().bsi_debug_bins(field, _ptr(pos), P, tile, _ptr(hist), _ptr(offs), _ptr(perm),
+                                _ptr(pos_sorted), ctypes.byref(n), stream), "bsi_debug_bins")
+    return n.value
 
 
 def bsi_field_stats(field):

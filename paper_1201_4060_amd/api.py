@@ -106,6 +106,18 @@ class Field:
             _bsi.bsi_debug_cells(self.handle, pos, P, cell, t, _stream())
         return cell, t
 
+    def debug_bins(self, pos, tile):
+        """The evaluation's binning of pos by Morton tiles of `tile` cells:
+        (hist, offs, perm, pos_sorted) device tensors (bsi_debug_bins)."""
+        P = pos.shape[0]
+        nb = _bsi.bsi_debug_bins(self.handle, None, P, tile, None, None, None, None, _stream())
+        hist = torch.empty(nb, dtype=torch.int32, device=pos.device)
+        offs = torch.empty(nb, dtype=torch.int32, device=pos.device)
+        perm = torch.empty(P, dtype=torch.int32, device=pos.device)
+        ps = torch.empty((P, 3), dtype=torch.float64, device=pos.device)
+        _bsi.bsi_debug_bins(self.handle, pos, P, tile, hist, offs, perm, ps, _stream())
+        return hist, offs, perm, ps
+
     def nonfinite_count(self):
         return _bsi.bsi_field_stats(self.handle)
 

@@ -1,4 +1,5 @@
 // C ABI of the bsi library: contexts, fields, validation, caches.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -404,6 +405,27 @@ bsi_status bsi_debug_cells(bsi_field* f, const double* pos, int64_t P, int32_t* 
     BSI_TRY(check_device_ptr(t, "t"));
     BSI_HIP(hipSetDevice(f->ctx->device));
     return debug_cells_run(f, pos, P, cell, t, pick_stream(f->ctx, stream));
+}
+
+bsi_status bsi_debug_bins(bsi_field* f, const double* pos, int64_t P, int32_t tile, uint32_t* hist,
+                          uint32_t* offs, uint32_t* perm, double* pos_sorted, int64_t* nbuckets, void* stream) {
+    clear_error();
+    BSI_CHECK(f != nullptr && nbuckets != nullptr, BSI_E_INVAL, "NULL argument");
+    BSI_CHECK(P >= 0 && P < (int64_t(1) << 31), BSI_E_INVAL, "P must be in [0, 2^31)");
+    const int nmax = std::max(f->n[0], std::max(f->n[1], f->n[2]));
+    BSI_CHECK(tile >= 1 && tile >= (nmax + 255) / 256, BSI_E_INVAL,
+              "tile must be >= 1 and >= ceil(max(n) / 256)");
+    *nbuckets = int64_t(bsi::bin_bucket_count(f, tile) + 1);
+    if (hist == nullptr) return BSI_OK;
+    BSI_TRY(check_device_ptr(hist, "hist"));
+    BSI_TRY(check_device_ptr(offs, "offs"));
+    if (P > 0) {
+        BSI_TRY(check_device_ptr(pos, "pos"));
+        BSI_TRY(check_device_ptr(perm, "perm"));
+        BSI_TRY(check_device_ptr(pos_sorted, "pos_sorted"));
+    }
+    BSI_HIP(hipSetDevice(f->ctx->device));
+    return debug_bins_run(f, pos, P, tile, hist, offs, perm, pos_sorted, pick_stream(f->ctx, stream));
 }
 
 bsi_status bsi_field_stats(bsi_field* f, int64_t* nonfinite) {

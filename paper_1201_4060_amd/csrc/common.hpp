@@ -212,5 +212,9 @@ bsi_status lookup_config(bsi_ctx* ctx, const bsi_field* f, int64_t P, bsi_eval_c
 bsi_status check_device_ptr_ex(const void* p, const char* what);
 bsi_status debug_cells_run(bsi_field* f, const double* pos, int64_t P, int32_t* cell, double* t,
                            hipStream_t s);
+// the evaluation's binning alone, results copied to caller buffers
+size_t bin_bucket_count(const bsi_field* f, int tile);
+bsi_status debug_bins_run(bsi_field* f, const double* pos, int64_t P, int tile, uint32_t* hist, uint32_t* offs,
+                          uint32_t* perm, double* pos_sorted, hipStream_t s);
 
 }  // namespace bsi

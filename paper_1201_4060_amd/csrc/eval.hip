@@ -373,4 +373,26 @@ bsi_status debug_cells_run(bsi_field* f, const double* pos, int64_t P, int32_t* 
     return BSI_OK;
 }
 
+bsi_status debug_bins_run(bsi_field* f, const double* pos, int64_t P, int tile, uint32_t* hist, uint32_t* offs,
+                          uint32_t* perm, double* pos_sorted, hipStream_t s) {
+    const size_t nb = bin_bucket_count(f, tile) + 1;
+    if (P == 0) {
+        BSI_HIP(hipMemsetAsync(hist, 0, nb * sizeof(uint32_t), s));
+        BSI_HIP(hipMemsetAsync(offs, 0, nb * sizeof(uint32_t), s));
+        return BSI_OK;
+    }
+    const BinLayout l = bin_layout(f, P, tile);
+    void* ws = nullptr;
+    BSI_TRY(get_workspace(f->ctx->eval_ws, s, l.bytes, &ws));
+    char* w = static_cast<char*>(ws);
+    BSI_TRY(bin_run(f, pos, P, tile, w + l.grp, reinterpret_cast<uint32_t*>(w + l.perm),
+                    reinterpret_cast<double*>(w + l.pos), reinterpret_cast<uint32_t*>(w + l.hist),
+                    reinterpret_cast<uint32_t*>(w + l.offs), s));
+    BSI_HIP(hipMemcpyAsync(hist, w + l.hist, nb * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    BSI_HIP(hipMemcpyAsync(offs, w + l.offs, nb * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    BSI_HIP(hipMemcpyAsync(perm, w + l.perm, size_t(P) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    BSI_HIP(hipMemcpyAsync(pos_sorted, w + l.pos, size_t(P) * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return BSI_OK;
+}
+
 }  // namespace bsi
