@@ -150,3 +150,59 @@ def test_admission_by_budget_and_errors(served):
             bsi._bsi.bsi_server_submit(sv.handle, 0, p, 0, u)
         with pytest.raises(bsi.BsiError):
             sv.add_field(0, fields[0])
+
+
+def test_served_full_size(served):
+    """The serving workload's sizes: a 1024^3 x3 snapshot (order 6) and a 256^3 x3
+    one (order 4), FP32, from the device spectrum generator; requests of 10^3 to
+    10^6 uniform or clustered particles served while others run, each bitwise
+    equal to its stand-alone evaluation."""
+    import torch
+    import paper_1201_4060_amd as bsi
+    ctx, _ = served
+    fields = {}
+    try:
+        for fid, (n, N) in enumerate(((1024, 6), (256, 4))):
+            spec = torch.empty((3, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+            bsi._bsi.bsi_synth_kolmogorov(ctx.handle, n, 3, 500 + fid, spec)
+            f = bsi.Field(ctx, n, 3, N, bsi.BSI_F32)
+            f.set_spectrum(spec)
+            fields[fid] = f
+            del spec
+        torch.cuda.synchronize()
+        log(f"  resident: 1024^3 and 256^3 snapshots, "
+            f"{sum(bsi._bsi.bsi_field_bytes(f.handle) for f in fields.values()) / 2**30:.1f} GiB of grids")
+        reqs = []
+        for k, (fid, P, clustered) in enumerate(((0, 1_000_000, False), (1, 1000, True), (0, 100_000, True),
+                                                (1, 1_000_000, False), (0, 3000, False), (1, 250_000, True))):
+            pos = synth.clustered_positions(P // 2, 4, P // 8, 0.1, seed=620 + k) if clustered else \
+                synth.uniform_positions(P, seed=620 + k)
+            pos = pos[:P]
+            p = _pinned((P, 3), torch.float64)
+            p.numpy()[:] = pos
+            u = _pinned((P, 3), torch.float32)
+            g = _pinned((P, 3, 3), torch.float32)
+            u.fill_(float("nan"))
+            g.fill_(float("nan"))
+            reqs.append((fid, p, u, g))
+        with bsi.Server(ctx, hbm_budget=1 << 30, max_slots=4) as sv:
+            for fid, f in fields.items():
+                sv.add_field(fid, f)
+            tickets = [sv.submit(fid, p, u, g) for fid, p, u, g in reqs]
+            for t in tickets:
+                sv.wait(t)
+            st = sv.stats()
+            assert st["completed"] == len(reqs) and st["failed"] == 0
+        for k, (fid, p, u, g) in enumerate(reqs):
+            f = fields[fid]
+            P = p.shape[0]
+            cfg = bsi._bsi.bsi_ctx_lookup_config(ctx.handle, f.handle, P)
+            ua, ga = f.eval(p.cuda(), cfg=cfg)
+            torch.cuda.synchronize()
+            assert not np.isnan(u.numpy()).any()
+            assert np.array_equal(u.numpy(), host(ua)) and np.array_equal(g.numpy(), host(ga)), \
+                f"request {k} (field {fid}, P={P}) differs from its stand-alone result"
+            log(f"  request {k}: field {fid}, P={P}: bitwise equal to stand-alone")
+    finally:
+        for f in fields.values():
+            f.close()
