@@ -80,6 +80,16 @@ def gather_bytes(P_, C, U, coef_bytes, out_bytes=4):
     return P_ * (24 + 4 * C * out_bytes) + U * C * coef_bytes
 
 
+# FP32 FMA rate of the vector ALUs without packed FP32 (256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz); the library is compiled without packed FP32 instructions
+FMA_PEAK_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def gather_fma(N, C):
+    """FMAs per particle of the u + grad u contraction (leading term 6N^3 for C = 3)."""
+    return 6 * N ** 3 + 15 * N ** 2 + 12 * N if C == 3 else 2 * N ** 3 + 9 * N ** 2 + 4 * N
+
+
 def fft_bytes(stage, n, C, order, spec_bytes=16, work_bytes=8, grid_bytes=4):
     """Algorithmic bytes of one FFT pass (spectrum read, work array, grid written)."""
     half = n * n * (n // 2 + 1) * C
@@ -349,6 +359,10 @@ def form_plain(args):
                             "frac_of_copy": round(e["achieved"] / copy_gbs, 4),
                             "algorithmic_bytes": alg[k], "distinct_points": U[o], "avg_us": e["avg_us"],
                             "points_per_s": round(P / (stages[k]["avg_us"] * 1e-6), 1)}
+            fma_s = P * gather_fma(o, NCOMP) / (stages[k]["avg_us"] * 1e-6)
+            gather_rl[k]["alu"] = {"fma_per_particle": gather_fma(o, NCOMP), "achieved_TFMA_s": round(fma_s / 1e12, 3),
+                                   "peak_TFMA_s": round(FMA_PEAK_PER_S / 1e12, 3),
+                                   "frac": round(fma_s / FMA_PEAK_PER_S, 4)}
             if k in cold:
                 c = roofline_entry(k, alg[k], cold[k]["avg_us"])
                 gather_rl[k]["cold"] = {"avg_us": c["avg_us"], "achieved_GBs": c["achieved"], "frac": c["frac"],
@@ -459,6 +473,7 @@ def form_precision(args):
         e = roofline_entry(f"gather@{k}", alg[f"gather@{k}"], g["avg_us"])
         per[k] = {"gather_us": e["avg_us"], "gather_achieved_GBs": e["achieved"], "gather_frac": e["frac"],
                   "gather_points_per_s": round(Pp / (g["avg_us"] * 1e-6), 1),
+                  "gather_alu_frac": round(Pp * gather_fma(N, C) / (g["avg_us"] * 1e-6) / FMA_PEAK_PER_S, 4),
                   "grid_bytes": fields[k].nbytes()}
     # errors against the FP64 oracle on a sample (outside the timed region);
     # the same oracle work is the CPU baseline

@@ -99,3 +99,10 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_gather_fma_count():
+    # 6N^3 + 15N^2 + 12N for three components: 672 (N = 4), 1908 (N = 6)
+    assert bench.gather_fma(4, 3) == 672 and bench.gather_fma(6, 3) == 1908
+    assert bench.gather_fma(4, 1) == 2 * 64 + 9 * 16 + 16
+    assert bench.FMA_PEAK_PER_S == pytest.approx(39.32e12, rel=1e-3)
