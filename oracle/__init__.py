@@ -19,7 +19,8 @@ methods for spectral codes" (SIAM J. Sci. Comput. 2012) defines:
                   FFT (Section 7, 3D multiplication and method statement);
 * ``evaluate`` -- stencil selection (Section 5, nearest-grid-point rule) and
                   the direct triple sum of weights times coefficients
-                  (Section 3, n-mode products), with first derivatives;
+                  (Section 3, n-mode products), with first derivatives,
+                  and with second derivatives (M^(2) = M D^2, Section 2);
 * ``theory``   -- per-mode relative L2 errors (Section 5) used as pins.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against values fixed by
@@ -30,7 +31,8 @@ from .bspline import (bspline_matrix, derivative_matrix, matrix_f64,
                       derivative_matrix_f64)
 from .symbol import sinc_power_sum, prefilter_constants, INTERP, L2OPT
 from .prefilter import prefilter
-from .evaluate import cells, weights, evaluate, inv_spacing, TWO_PI
+from .evaluate import (cells, weights, weights2, evaluate, evaluate_hessian, inv_spacing, TWO_PI,
+                       HESS_PAIRS)
 from . import theory
 
 __all__ = [

@@ -74,6 +74,14 @@ def weights(t, N, inv_h=1.0):
     return w, wd
 
 
+def weights2(t, N, inv_h=1.0):
+    """Second-derivative weights w''[P][N]: Section 2 with l = 2, M^(2) = M D^2,
+    times the chain factor (n/L)^2."""
+    M2 = derivative_matrix_f64(N, 2)
+    powers = np.stack([t ** i for i in range(N)], axis=-1)
+    return (powers @ M2.T) * (inv_h * inv_h)
+
+
 def stencil_indices(cell_d, N, n):
     """Periodic grid indices of the N stencil points along one axis, [P][N]."""
     j = np.arange(N, dtype=np.int64)
@@ -120,3 +128,66 @@ def evaluate(grid, pos, N, lengths=(TWO_PI, TWO_PI, TWO_PI), derivatives=True):
         if derivatives:
             grad[~finite] = np.nan
     return (u, grad) if derivatives else u
+
+
+# the six distinct second derivatives d2/dx_i dx_j, i <= j, in this order
+HESS_PAIRS = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
+
+
+def evaluate_hessian(grid, pos, N, lengths=(TWO_PI, TWO_PI, TWO_PI)):
+    """u, grad u and the second derivatives of the interpolant at positions.
+
+    Section 2: the l-th derivative of the interpolant on a cell uses M^(l) = M D^l;
+    in three dimensions (Section 3) a mixed second derivative d2/dx_i dx_j
+    replaces the weights of axes i and j by their first-derivative weights, and
+    d2/dx_i^2 those of axis i by its second-derivative weights.  Plain triple sum
+    over the N^3 stencil, as in evaluate().
+
+    Returns u [P][C], grad [P][C][3] and hess [P][C][6] with hess[p][c][m] =
+    d2 u_c / dx_i dx_j for (i, j) = HESS_PAIRS[m].  Particles with a non-finite
+    coordinate get NaN.
+    """
+    if N % 2:
+        raise ValueError("only even spline orders are supported")
+    grid = np.asarray(grid, dtype=np.float64)
+    C, n0, n1, n2 = grid.shape
+    shape = (n0, n1, n2)
+    pos = np.asarray(pos, dtype=np.float64)
+    P = pos.shape[0]
+    cell, t, finite = cells(pos, shape, lengths)
+    W, Wd, Wdd, idx = [], [], [], []
+    for d in range(3):
+        ih = inv_spacing(shape[d], lengths[d])
+        w, wd = weights(t[:, d], N, ih)
+        W.append(w)
+        Wd.append(wd)
+        Wdd.append(weights2(t[:, d], N, ih))
+        idx.append(stencil_indices(cell[:, d], N, shape[d]))
+    flat = grid.reshape(C, -1)
+    u = np.zeros((P, C))
+    grad = np.zeros((P, C, 3))
+    hess = np.zeros((P, C, 6))
+    for a in range(N):
+        for b in range(N):
+            for e in range(N):
+                lin = (idx[0][:, a] * n1 + idx[1][:, b]) * n2 + idx[2][:, e]
+                vals = flat[:, lin].T
+                j = (a, b, e)
+                u += (W[0][:, a] * W[1][:, b] * W[2][:, e])[:, None] * vals
+                for d in range(3):
+                    f = [W[k][:, j[k]] for k in range(3)]
+                    f[d] = Wd[d][:, j[d]]
+                    grad[:, :, d] += (f[0] * f[1] * f[2])[:, None] * vals
+                for m, (p_, q_) in enumerate(HESS_PAIRS):
+                    f = [W[k][:, j[k]] for k in range(3)]
+                    if p_ == q_:
+                        f[p_] = Wdd[p_][:, j[p_]]
+                    else:
+                        f[p_] = Wd[p_][:, j[p_]]
+                        f[q_] = Wd[q_][:, j[q_]]
+                    hess[:, :, m] += (f[0] * f[1] * f[2])[:, None] * vals
+    if not finite.all():
+        u[~finite] = np.nan
+        grad[~finite] = np.nan
+        hess[~finite] = np.nan
+    return u, grad, hess

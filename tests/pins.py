@@ -56,6 +56,12 @@ def bspline_deriv_float(N, y):
     return bspline_float(N - 1, y + 0.5) - bspline_float(N - 1, y - 0.5)
 
 
+def bspline_deriv2_float(N, y):
+    """B_N''(y) from two differences of the Cox-de Boor B_(N-2)."""
+    y = np.asarray(y, dtype=np.float64)
+    return bspline_float(N - 2, y + 1.0) - 2.0 * bspline_float(N - 2, y) + bspline_float(N - 2, y - 1.0)
+
+
 def gauss_legendre_cells(n, per_cell):
     """Nodes and weights of a composite Gauss-Legendre rule on [0, n)."""
     x, w = np.polynomial.legendre.leggauss(per_cell)

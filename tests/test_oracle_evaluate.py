@@ -226,3 +226,84 @@ def test_convergence_order(N):
     assert abs(su[-1] - N) < 0.1 and np.all(su > N - 0.1), su
     assert abs(sg[-1] - (N - 1)) < 0.1 and np.all(sg > N - 1.1), sg
     assert np.all(np.diff(su) < 0) and np.all(np.diff(sg) < 0)
+
+
+# ---- second derivatives (M^(2) = M D^2) ------------------------------------
+
+def _brute_force_hessian(grid, pos, N, L=TWO_PI):
+    from pins import bspline_deriv2_float
+    C, n0, n1, n2 = grid.shape
+    shape = (n0, n1, n2)
+    W, Wd, Wdd = [], [], []
+    for d in range(3):
+        n = shape[d]
+        s = pos[:, d] * (n / L)
+        g = np.arange(n)
+        w, wd, wdd = (np.zeros((pos.shape[0], n)) for _ in range(3))
+        for m in range(-8, 9):
+            y = s[:, None] - (g[None, :] + m * n)
+            w += bspline_float(N, y)
+            wd += bspline_deriv_float(N, y) * (n / L)
+            wdd += bspline_deriv2_float(N, y) * (n / L) ** 2
+        W.append(w)
+        Wd.append(wd)
+        Wdd.append(wdd)
+    out = []
+    for i, j in ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)):
+        f = list(W)
+        if i == j:
+            f[i] = Wdd[i]
+        else:
+            f[i], f[j] = Wd[i], Wd[j]
+        out.append(np.einsum("pa,pb,pe,cabe->pc", f[0], f[1], f[2], grid))
+    return np.stack(out, axis=-1)
+
+
+@pytest.mark.parametrize("N", [4, 6])
+@pytest.mark.parametrize("shape", [(8, 10, 12), (12, 12, 12)])
+def test_hessian_all_lattice_brute_force(N, shape):
+    from oracle import evaluate_hessian
+    rng = np.random.default_rng(15)
+    grid = rng.standard_normal((2,) + shape)
+    pos = _edge_positions(rng, 40)
+    u, g, h = evaluate_hessian(grid, pos, N)
+    u1, g1 = evaluate(grid, pos, N)
+    assert np.array_equal(u, u1) or np.max(np.abs(u - u1)) < 1e-13 * np.max(np.abs(grid))
+    assert np.max(np.abs(g - g1)) < 1e-12 * np.max(np.abs(grid))
+    hb = _brute_force_hessian(grid, pos, N)
+    scale = np.max(np.abs(grid)) * (max(shape) / TWO_PI) ** 2
+    assert np.max(np.abs(h - hb)) < 1e-11 * scale
+
+
+@pytest.mark.parametrize("N", [4, 6])
+def test_hessian_polynomial_reproduction(N):
+    # the grid of test_polynomial_reproduction reproduces s0^a s1^b s2^c
+    # exactly, so its second derivatives are reproduced exactly too
+    from oracle import evaluate_hessian
+    n = 32
+    degs = (N - 1, 1, N - 2)
+    qs = [_reproducing_coeffs(k, N) for k in degs]
+    J = np.arange(n, dtype=np.float64)
+    vals = [sum(c * J ** m for m, c in enumerate(q)) for q in qs]
+    grid = np.einsum("a,b,e->abe", vals[0], vals[1], vals[2])[None]
+    h = TWO_PI / n
+    pos = np.random.default_rng(19).uniform(N * h, (n - N) * h, size=(200, 3))
+    _, _, hess = evaluate_hessian(grid, pos, N)
+    s = pos / h
+
+    def mono(d0, d1, d2):
+        out = np.ones(pos.shape[0])
+        for ax, dd in enumerate((d0, d1, d2)):
+            k = degs[ax]
+            coef = 1.0
+            for r in range(dd):
+                coef *= (k - r)
+            out = out * (coef * s[:, ax] ** (k - dd) if k >= dd else 0.0)
+        return out / h ** (d0 + d1 + d2)
+
+    exact = np.stack([mono(2, 0, 0), mono(1, 1, 0), mono(1, 0, 1), mono(0, 2, 0), mono(0, 1, 1),
+                      mono(0, 0, 2)], axis=-1)
+    scale = np.abs(exact).max()          # d2/ds1^2 of s1^1 is exactly zero
+    for m in range(6):
+        assert np.max(np.abs(hess[:, 0, m] - exact[:, m])) < 1e-12 * scale, m
+    assert np.abs(exact[:, 3]).max() == 0.0 and np.abs(exact[:, 0]).max() > 0.0
