@@ -155,6 +155,17 @@ bsi_status bsi_eval_ex(bsi_field* field, const double* pos_dev, int64_t P,
                        void* u_dev, void* grad_dev, const bsi_eval_config* cfg,
                        void* hip_stream);
 
+/* u, grad u and the second derivatives at P particles (Section 2: the l-th
+ * derivative of the interpolant uses M^(l) = M D^l, here l = 2; Section 3 for
+ * the tensor product).  u_dev [P][ncomp], grad_dev [P][ncomp][3] (NULL = not
+ * computed), hess_dev [P][ncomp][6] with hess[p][c][m] = d2 u_c / dx_i dx_j for
+ * (i, j) = (0,0), (0,1), (0,2), (1,1), (1,2), (2,2); physical units (each
+ * derivative carries n/L of its axis).  Element type as for bsi_eval; same
+ * validation, non-finite handling and asynchrony.  The particles are binned
+ * with the context's evaluation workspace of the stream. */
+bsi_status bsi_eval_hessian(bsi_field* field, const double* pos_dev, int64_t P, void* u_dev,
+                            void* grad_dev, void* hess_dev, void* hip_stream);
+
 /* Cell index and offset of each particle per axis, exactly as the evaluation
  * computes them (Section 5 stencil rule): s = x * (n/L) (one FP64 product),
  * f = floor(s), t = s - f, cell = f mod n in [0, n).  cell_dev: int32 [P][3],

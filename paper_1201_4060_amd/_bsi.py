@@ -90,6 +90,7 @@ SIGNATURES = {
     "bsi_eval": (ST, [VP, VP, I64, VP, VP, VP]),
     "bsi_eval_ex": (ST, [VP, VP, I64, VP, VP, ctypes.POINTER(EvalConfig), VP]),
     "bsi_debug_cells": (ST, [VP, VP, I64, VP, VP, VP]),
+    "bsi_eval_hessian": (ST, [VP, VP, I64, VP, VP, VP, VP]),
     "bsi_debug_bins": (ST, [VP, VP, I64, I32, VP, VP, VP, VP, ctypes.POINTER(I64), VP]),
     "bsi_field_stats": (ST, [VP, ctypes.POINTER(I64)]),
     "bsi_ctx_set_timing": (ST, [VP, I32]),
@@ -216,6 +217,11 @@ def bsi_eval(field, pos, P, u, grad=None, stream=None):
 def bsi_eval_ex(field, pos, P, u, grad=None, cfg=None, stream=None):
     c = ctypes.byref(cfg) if cfg is not None else None
     _check(lib().bsi_eval_ex(field, _ptr(pos), P, _ptr(u), _ptr(grad), c, stream), "bsi_eval_ex")
+
+
+def bsi_eval_hessian(field, pos, P, u, grad, hess, stream=None):
+    _check(lib().bsi_eval_hessian(field, _ptr(pos), P, _ptr(u), _ptr(grad), _ptr(hess), stream),
+           "bsi_eval_hessian")
 
 
 def bsi_debug_cells(field, pos, P, cell, t, stream=None):

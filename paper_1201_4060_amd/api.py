@@ -98,6 +98,22 @@ class Field:
             _bsi.bsi_eval_ex(self.handle, pos, P, u, g, cfg, _stream())
         return u, g
 
+    def eval_hessian(self, pos, grad=True, out=None):
+        """pos: float64 device tensor [P][3] -> (u [P][C], grad [P][C][3] or None,
+        hess [P][C][6]: d2/dx_i dx_j for (i, j) = 00, 01, 02, 11, 12, 22)."""
+        assert pos.is_cuda and pos.is_contiguous() and pos.dtype == torch.float64
+        assert pos.dim() == 2 and pos.shape[1] == 3
+        P = pos.shape[0]
+        if out is None:
+            u = torch.empty((P, self.ncomp), dtype=self.out_dtype, device=pos.device)
+            g = torch.empty((P, self.ncomp, 3), dtype=self.out_dtype, device=pos.device) if grad else None
+            h = torch.empty((P, self.ncomp, 6), dtype=self.out_dtype, device=pos.device)
+        else:
+            u, g, h = out
+        if P:
+            _bsi.bsi_eval_hessian(self.handle, pos, P, u, g, h, _stream())
+        return u, g, h
+
     def debug_cells(self, pos):
         P = pos.shape[0]
         cell = torch.empty((P, 3), dtype=torch.int32, device=pos.device)

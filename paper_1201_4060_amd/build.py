@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbsi.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "symbol.cpp", "fft.hip", "eval.hip", "batch.hip", "tune.hip", "synth.hip", "server.cpp"]
+SOURCES = ["api.cpp", "symbol.cpp", "fft.hip", "eval.hip", "hessian.hip", "batch.hip", "tune.hip", "synth.hip",
+           "server.cpp"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

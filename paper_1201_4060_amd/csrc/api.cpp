@@ -390,6 +390,22 @@ bsi_status bsi_eval_ex(bsi_field* f, const double* pos, int64_t P, void* u, void
     return eval_run(f, pos, P, u, grad, c, s);
 }
 
+bsi_status bsi_eval_hessian(bsi_field* f, const double* pos, int64_t P, void* u, void* grad, void* hess,
+                            void* stream) {
+    clear_error();
+    BSI_CHECK(f != nullptr, BSI_E_INVAL, "field is NULL");
+    BSI_CHECK(P >= 0 && P < (int64_t(1) << 31), BSI_E_INVAL, "P must be in [0, 2^31)");
+    if (P == 0) return BSI_OK;
+    BSI_TRY(check_device_ptr(pos, "pos"));
+    BSI_TRY(check_device_ptr(u, "u"));
+    BSI_TRY(check_device_ptr(hess, "hess"));
+    if (grad) BSI_TRY(check_device_ptr(grad, "grad"));
+    BSI_HIP(hipSetDevice(f->ctx->device));
+    hipStream_t s = pick_stream(f->ctx, stream);
+    f->last_stream = s;
+    return hessian_run(f, pos, P, u, grad, hess, s);
+}
+
 bsi_status bsi_eval(bsi_field* f, const double* pos, int64_t P, void* u, void* grad, void* stream) {
     return bsi_eval_ex(f, pos, P, u, grad, nullptr, stream);
 }

@@ -214,6 +214,17 @@ bsi_status debug_cells_run(bsi_field* f, const double* pos, int64_t P, int32_t* 
                            hipStream_t s);
 // the evaluation's binning alone, results copied to caller buffers
 size_t bin_bucket_count(const bsi_field* f, int tile);
+// byte offsets of the binning's arrays in its workspace (grouping scratch
+// first, 16-byte aligned), and the binning itself
+struct BinLayout {
+    size_t grp, pos, perm, hist, offs, bytes;
+};
+BinLayout bin_layout(const bsi_field* f, long P, int tile);
+bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, void* scratch, uint32_t* perm,
+                   double* pos_sorted, uint32_t* hist, uint32_t* offs, hipStream_t s);
+// u, grad u and the six second derivatives per component (hessian.hip)
+bsi_status hessian_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad, void* hess,
+                       hipStream_t s);
 bsi_status debug_bins_run(bsi_field* f, const double* pos, int64_t P, int tile, uint32_t* hist, uint32_t* offs,
                           uint32_t* perm, double* pos_sorted, hipStream_t s);
 

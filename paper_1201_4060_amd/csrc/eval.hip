@@ -219,11 +219,7 @@ static GrpPlan bin_plan(const bsi_field* f, long P, int tile, int* shift) {
 // Workspace of a binned evaluation (16-byte aligned): the grouping scratch,
 // then the binned positions (3P doubles), the permutation (P), the bucket
 // counts and first slots (nb each).
-struct BinLayout {
-    size_t grp, pos, perm, hist, offs, bytes;
-};
-
-static BinLayout bin_layout(const bsi_field* f, long P, int tile) {
+BinLayout bin_layout(const bsi_field* f, long P, int tile) {
     int shift = 0;
     const size_t nb = bin_bucket_count(f, tile) + 1;
     BinLayout l;

@@ -1,0 +1,113 @@
+"""Second derivatives of the interpolant on the GPU (bsi_eval_hessian) against
+the oracle's evaluate_hessian (M^(2) = M D^2, Section 2; tensor product, Section 3).
+
+Tolerances as for u and grad u: per output quantity, max |gpu - oracle| over
+the particles relative to max |oracle|, 1e-12 for FP64 grids and arithmetic,
+1e-5 for FP32 arithmetic (FP32 and BF16 grids, the oracle evaluated on the
+stored coefficients).
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import log, dev, host, rel_err, edge_positions, bf16_round, TOL_F32, TOL_F64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1201_4060_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _positions(P, seed):
+    return np.concatenate([synth.uniform_positions(P, seed=seed), edge_positions()])
+
+
+@pytest.mark.parametrize("N", [4, 6])
+@pytest.mark.parametrize("C", [1, 3])
+def test_hessian_f64(ctx, N, C):
+    import paper_1201_4060_amd as bsi
+    from oracle import prefilter, evaluate_hessian
+    n = 32
+    grid = prefilter(synth.kolmogorov_spectrum(n, C, seed=40 + C), N)
+    pos = _positions(6000, seed=41 + N)
+    with bsi.Field(ctx, n, C, N, bsi.BSI_F64) as f:
+        f.set_coefficients(dev(grid))
+        u, g, h = f.eval_hessian(dev(pos))
+        u1, g1 = f.eval(dev(pos))
+        u, g, h, u1, g1 = host(u), host(g), host(h), host(u1), host(g1)
+    wu, wg, wh = evaluate_hessian(grid, pos, N)
+    eu, eg, eh = rel_err(u, wu), rel_err(g, wg), rel_err(h, wh)
+    log(f"  f64 n={n} C={C} N={N}: max rel err u {eu.max():.2e} grad {eg.max():.2e} hess {eh.max():.2e}")
+    assert eu.max() < TOL_F64 and eg.max() < TOL_F64 and eh.max() < TOL_F64
+    # u and grad u agree with the evaluation entry point
+    assert rel_err(u, u1).max() < 1e-14 and rel_err(g, g1).max() < 1e-13
+
+
+@pytest.mark.parametrize("coef", ["f32", "bf16"])
+def test_hessian_f32_bf16(ctx, coef):
+    import paper_1201_4060_amd as bsi
+    from oracle import prefilter, evaluate_hessian
+    n, C, N = 48, 3, 6
+    grid = prefilter(synth.kolmogorov_spectrum(n, C, seed=50), N)
+    stored = grid.astype(np.float32).astype(np.float64) if coef == "f32" else bf16_round(grid)
+    pos = _positions(8000, seed=51)
+    dt = bsi.BSI_F32 if coef == "f32" else bsi.BSI_BF16
+    with bsi.Field(ctx, n, C, N, dt) as f:
+        f.set_coefficients(dev(grid))
+        u, g, h = f.eval_hessian(dev(pos))
+        u, g, h = host(u), host(g), host(h)
+    wu, wg, wh = evaluate_hessian(stored, pos, N)
+    eu, eg, eh = rel_err(u, wu), rel_err(g, wg), rel_err(h, wh)
+    log(f"  {coef} n={n}: max rel err u {eu.max():.2e} grad {eg.max():.2e} hess {eh.max():.2e}")
+    assert eu.max() < TOL_F32 and eg.max() < TOL_F32 and eh.max() < TOL_F32
+
+
+def test_hessian_nonfinite_empty_and_no_grad(ctx):
+    import torch
+    import paper_1201_4060_amd as bsi
+    from oracle import prefilter, evaluate_hessian
+    n, C, N = 16, 3, 4
+    grid = prefilter(synth.kolmogorov_spectrum(n, C, seed=60), N)
+    pos = np.concatenate([synth.uniform_positions(100, seed=61), [[np.nan, 0.0, 0.0], [0.0, np.inf, 1.0]]])
+    with bsi.Field(ctx, n, C, N, bsi.BSI_F64) as f:
+        f.set_coefficients(dev(grid))
+        before = f.nonfinite_count()
+        u, g, h = f.eval_hessian(dev(pos), grad=False)
+        assert g is None
+        u, h = host(u), host(h)
+        assert f.nonfinite_count() - before == 2
+        assert np.isnan(u[-2:]).all() and np.isnan(h[-2:]).all()
+        _, _, wh = evaluate_hessian(grid, pos[:-2], N)
+        assert rel_err(h[:-2], wh).max() < TOL_F64
+        u0, g0, h0 = f.eval_hessian(torch.empty((0, 3), dtype=torch.float64, device="cuda"))
+        assert h0.shape == (0, C, 6)
+
+
+def test_hessian_full_size_sampled(ctx):
+    # 256^3 x3, FP32 grid, order 6, 10^6 uniform particles (the Hessian
+    # benchmark's workload); the oracle on a sample of the particles
+    import paper_1201_4060_amd as bsi
+    from oracle import prefilter, evaluate_hessian
+    n, C, N = 256, 3, 6
+    log("hessian 256^3 x3 f32 N=6, 1e6 particles")
+    uhat = synth.kolmogorov_spectrum(n, C, seed=1)
+    grid = prefilter(uhat, N)
+    pos = synth.uniform_positions(1_000_000, seed=101)
+    with bsi.Field(ctx, n, C, N, bsi.BSI_F32) as f:
+        f.set_coefficients(dev(grid))
+        u, g, h = f.eval_hessian(dev(pos))
+        u, g, h = host(u), host(g), host(h)
+    assert np.isfinite(h).all()
+    sample = np.random.default_rng(7).choice(pos.shape[0], 3000, replace=False)
+    wu, wg, wh = evaluate_hessian(grid.astype(np.float32).astype(np.float64), pos[sample], N)
+    eu, eg, eh = rel_err(u[sample], wu), rel_err(g[sample], wg), rel_err(h[sample], wh)
+    log(f"  sampled max rel err u {eu.max():.2e} grad {eg.max():.2e} hess {eh.max():.2e}")
+    assert eu.max() < TOL_F32 and eg.max() < TOL_F32 and eh.max() < TOL_F32
+    # the field is divergence free: the trace of grad u is small (logged)
+    div = g[:, 0, 0] + g[:, 1, 1] + g[:, 2, 2]
+    log(f"  rms div / rms grad = {np.sqrt(np.mean(div ** 2) / np.mean(g ** 2)):.2e}")
