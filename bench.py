@@ -17,6 +17,7 @@ Other forms (one JSON line each, same keys):
                     from a HIP graph; beside it one launch per field
   --form serve      resident 1024^3 and 256^3 fields (both orders), Poisson
                     particle-query requests; points/s with p50/p99 latency
+  --form hessian    the default workload with second derivatives as well
   --form copy       1 GiB device copy (calibrates HBM byte counters)
 
 Prints one JSON line on stdout; diagnostics go to stderr.
@@ -88,6 +89,12 @@ FMA_PEAK_PER_S = 256 * 4 * 16 * 2.4e9
 def gather_fma(N, C):
     """FMAs per particle of the u + grad u contraction (leading term 6N^3 for C = 3)."""
     return 6 * N ** 3 + 15 * N ** 2 + 12 * N if C == 3 else 2 * N ** 3 + 9 * N ** 2 + 4 * N
+
+
+def hessian_fma(N, C):
+    """FMAs per particle of the u + grad u + second-derivative contraction:
+    3 per coefficient along axis 2, 6 per row along axis 1, 10 per plane."""
+    return 3 * C * N ** 3 + 6 * C * N ** 2 + 10 * C * N
 
 
 def fft_bytes(stage, n, C, order, spec_bytes=16, work_bytes=8, grid_bytes=4):
@@ -399,6 +406,112 @@ def form_plain(args):
                      streams=args.streams, ms_per_step_one_stream=round(sps_one * 1e3, 4),
                      gather_roofline=gather_rl, fft_roofline=fft_rl, per_order=per_order,
                      copy_GBs=round(copy_gbs, 1),
+                     stages_us={k: round(v["avg_us"], 2) for k, v in stages.items()})
+
+
+# ---------------------------------------------------------- hessian form ---
+
+def form_hessian(args):
+    """The plain workload with second derivatives: 256^3 x3 FP32 grid, orders 4
+    and 6, 10^6 uniform particles; step = prefilter + u, grad u and the six
+    second derivatives per component, per order (the orders on two streams)."""
+    import torch
+    from threadpoolctl import threadpool_limits
+    import synth
+    import paper_1201_4060_amd as bsi
+    dev = torch.device("cuda:0")
+    eprint("generating inputs ...")
+    uhat_np = synth.kolmogorov_spectrum(N_GRID, NCOMP, seed=FIELD_SEED)
+    pos_np = synth.uniform_positions(P, seed=POS_SEED)
+    uhat = torch.from_numpy(uhat_np).to(dev)
+    pos = torch.from_numpy(pos_np).to(dev)
+    ctxs = {o: bsi.Context(0) for o in ORDERS}
+    fields = {o: bsi.Field(ctxs[o], N_GRID, NCOMP, o, bsi.BSI_F32) for o in ORDERS}
+    outs = {o: (torch.empty((P, NCOMP), dtype=torch.float32, device=dev),
+                torch.empty((P, NCOMP, 3), dtype=torch.float32, device=dev),
+                torch.empty((P, NCOMP, 6), dtype=torch.float32, device=dev)) for o in ORDERS}
+
+    def order_part(o):
+        def run():
+            fields[o].set_spectrum(uhat)
+            fields[o].eval_hessian(pos, out=outs[o])
+        return run
+
+    def step_one_stream():
+        for o in ORDERS:
+            order_part(o)()
+
+    sides = [torch.cuda.Stream() for _ in ORDERS[1:]]
+    parts = [order_part(o) for o in ORDERS]
+
+    def step():
+        if args.streams > 1:
+            overlapped(parts, sides)
+        else:
+            step_one_stream()
+
+    sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi, stage_timing=False)
+    pct = dict(STEP_PERCENTILES)
+    sps_inst = timed_steps(step_one_stream, 1, args.steps, list(ctxs.values()), bsi)
+    STEP_PERCENTILES.clear()
+    STEP_PERCENTILES.update(pct)
+    stages = {}
+    for o in ORDERS:
+        stages.update(read_stages(bsi, ctxs[o], f"N{o}", names=STAGES + ("gather_hess",)))
+        bsi._bsi.bsi_ctx_set_timing(ctxs[o].handle, False)
+    eprint(f"{sps * 1e3:.3f} ms/step on {args.streams} stream(s), {sps_inst * 1e3:.3f} on one stream "
+           f"with stage events")
+    print_stages(stages, sps_inst, args.steps)
+    U = {o: distinct_stencil_points(pos, N_GRID, o) for o in ORDERS}
+    alg = {}
+    for k in stages:
+        st, o = k.split("@N")
+        o = int(o)
+        if st == "gather_hess":
+            # positions in; u, grad u and six second derivatives out (10 C values)
+            alg[k] = P * (24 + 10 * NCOMP * 4) + U[o] * NCOMP * 4
+        else:
+            alg[k] = fft_bytes(st, N_GRID, NCOMP, o)
+    dom = max((k for k in stages if alg[k] is not None), key=lambda k: stages[k]["total_ms"])
+    roofline = roofline_entry(dom, alg[dom], stages[dom]["avg_us"])
+    hess_rl = {}
+    for o in ORDERS:
+        k = f"gather_hess@N{o}"
+        e = roofline_entry(k, alg[k], stages[k]["avg_us"])
+        fma_s = P * hessian_fma(o, NCOMP) / (stages[k]["avg_us"] * 1e-6)
+        hess_rl[k] = {"achieved_GBs": e["achieved"], "frac": e["frac"], "avg_us": e["avg_us"],
+                      "algorithmic_bytes": alg[k], "fma_per_particle": hessian_fma(o, NCOMP),
+                      "alu_frac": round(fma_s / FMA_PEAK_PER_S, 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = 20000
+        idx = np.random.default_rng(0).choice(P, sample, replace=False)
+        total = 0.0
+        with threadpool_limits(limits=1):
+            for o in ORDERS:
+                t0 = time.perf_counter()
+                grid = oracle.prefilter(uhat_np, o)
+                t1 = time.perf_counter()
+                oracle.evaluate_hessian(grid, pos_np[idx], o)
+                t2 = time.perf_counter()
+                del grid
+                total += (t1 - t0) + (t2 - t1) * (P / sample)
+                eprint(f"cpu oracle order {o}: prefilter {t1 - t0:.2f} s, hessian of {sample} particles "
+                       f"{t2 - t1:.2f} s")
+        cpu = {"value": len(ORDERS) * P / total, "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": (f"full FP64 prefilter of the 256^3x3 field per order + u, grad u and second "
+                          f"derivatives of {sample} of the 1e6 particles per order, scaled to 1e6; numpy, "
+                          f"one thread")}
+    for o in ORDERS:
+        fields[o].close()
+        ctxs[o].close()
+    config = {"workload": "256^3 x3 divergence-free Kolmogorov field, FP32 grid, orders 4 and 6, 1e6 uniform "
+                          "particles; step = prefilter + u, grad u and second derivatives per order",
+              "n": N_GRID, "ncomp": NCOMP, "orders": list(ORDERS), "particles": P, "grid_dtype": "f32",
+              "outputs": "u, grad u, hessian (6 per component)", "parallelism": "single GPU"}
+    return base_line(args, len(ORDERS) * P / sps, "points/s", sps, "f32", config, roofline, cpu,
+                     streams=args.streams, hessian_roofline=hess_rl,
                      stages_us={k: round(v["avg_us"], 2) for k, v in stages.items()})
 
 
@@ -798,7 +911,8 @@ def copy_calibration(steps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--form", choices=("plain", "precision", "batch", "serve", "copy"), default="plain")
+    ap.add_argument("--form", choices=("plain", "precision", "batch", "serve", "hessian", "copy"),
+                    default="plain")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=100000)
@@ -824,7 +938,8 @@ def main():
         return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    form = {"plain": form_plain, "precision": form_precision, "batch": form_batch, "serve": form_serve}
+    form = {"plain": form_plain, "precision": form_precision, "batch": form_batch, "serve": form_serve,
+            "hessian": form_hessian}
     print(json.dumps(form[args.form](args)), flush=True)
 
 

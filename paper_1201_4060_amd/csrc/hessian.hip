@@ -5,10 +5,11 @@
 // (Section 3) the mixed derivative d2/dx_i dx_j takes the first-derivative
 // weights on axes i and j, and d2/dx_i^2 the second-derivative weights on
 // axis i; every factor carries the chain factor n/L of its axis.  The
-// particles are binned as for the evaluation (Morton tiles) and then gathered
-// one lane per particle straight from the grid, the contraction reducing axis
-// 2 first, then axis 1, then axis 0 (the Table 1 idea), with six per-plane
-// partial sums per component instead of three.
+// particles are binned as for the evaluation (Morton tiles of 8^3 cells) and
+// gathered from an LDS copy of each tile's block of the grid (or, for classes
+// without a tiled body, one lane per particle straight from the grid), the
+// contraction reducing axis 2 first, then axis 1, then axis 0 (the Table 1
+// idea), with six per-plane partial sums per component instead of three.
 //
 // Output per particle p and component c: u[p][c], grad[p][c][d] and
 // hess[p][c][m] = d2 u_c / dx_i dx_j for (i, j) = (0,0), (0,1), (0,2), (1,1),
@@ -53,6 +54,9 @@ struct HessArgs {
     const void* grid;
     const double* pos_sorted;  // positions in binned order
     const uint32_t* perm;      // particle of every binned slot
+    const uint32_t* hist;      // particles per Morton tile (tiled kernel)
+    const uint32_t* offs;      // first binned slot per Morton tile (tiled kernel)
+    uint32_t nbf;              // finite tiles; tile nbf holds the particles without a cell
     long P;
     int n0, n1, n2, P1;
     long pitch2;
@@ -181,6 +185,259 @@ __global__ __launch_bounds__(HESS_B) void k_gather_hess(HessArgs a) {
     }
 }
 
+// Cell and weights (value, first and second derivative, chain factors
+// included) of the particle at x; false when it has no cell.
+template <int N, typename AT>
+__device__ __forceinline__ bool hess_setup(const HessArgs& a, const double* x, int* cell, AT (*w)[N],
+                                           AT (*wd)[N], AT (*wdd)[N]) {
+    const int n[3] = {a.n0, a.n1, a.n2};
+    const double ih[3] = {a.ih0, a.ih1, a.ih2};
+    double t[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ok = cell_of(x[d], ih[d], n[d], cell[d], t[d]) && ok;
+    if (!ok) return false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        bspline_weights<N, AT>(AT(t[d]), w[d], wd[d]);
+        bspline_weights2<N, AT>(AT(t[d]), wdd[d]);
+        const AT s = AT(ih[d]);
+        const AT s2 = AT(ih[d] * ih[d]);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            wd[d][k] *= s;
+            wdd[d][k] *= s2;
+        }
+    }
+    return true;
+}
+
+// Sums over axis-0 planes: u, the three first and six second derivatives.
+template <typename AT, int C>
+struct HessSums {
+    AT s[10][C];
+};
+
+// Planes k = 0..NP-1 with axis-0 weights w0[k], wd0[k], wdd0[k] and rows
+// row(k, ib), accumulated in plane order into out (axis 2 first, then 1).
+template <int N, typename CT, typename AT, int C, int NP, typename RowFn>
+__device__ __forceinline__ void hess_planes(const AT* w0, const AT* wd0, const AT* wdd0, const AT (*w)[N],
+                                            const AT (*wd)[N], const AT (*wdd)[N], RowFn row,
+                                            HessSums<AT, C>& out) {
+#pragma unroll
+    for (int m = 0; m < 10; ++m)
+#pragma unroll
+        for (int c = 0; c < C; ++c) out.s[m][c] = AT(0);
+#pragma unroll 1
+    for (int k = 0; k < NP; ++k) {
+        AT a0 = w0[0], d0 = wd0[0], dd0 = wdd0[0];
+#pragma unroll
+        for (int q = 1; q < NP; ++q) {
+            a0 = k == q ? w0[q] : a0;
+            d0 = k == q ? wd0[q] : d0;
+            dd0 = k == q ? wdd0[q] : dd0;
+        }
+        AT v[C], v1[C], v2[C], v11[C], v12[C], v22[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = v1[c] = v2[c] = v11[c] = v12[c] = v22[c] = AT(0);
+#pragma unroll
+        for (int ib = 0; ib < N; ++ib) {
+            const CT* r = row(k, ib);
+            AT tr[C], trd[C], trdd[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) tr[c] = trd[c] = trdd[c] = AT(0);
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const AT val = widen<CT, AT>(r[e * C + c]);
+                    tr[c] += w[2][e] * val;
+                    trd[c] += wd[2][e] * val;
+                    trdd[c] += wdd[2][e] * val;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                v[c] += w[1][ib] * tr[c];
+                v1[c] += wd[1][ib] * tr[c];
+                v2[c] += w[1][ib] * trd[c];
+                v11[c] += wdd[1][ib] * tr[c];
+                v12[c] += wd[1][ib] * trd[c];
+                v22[c] += w[1][ib] * trdd[c];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            out.s[0][c] += a0 * v[c];
+            out.s[1][c] += d0 * v[c];
+            out.s[2][c] += a0 * v1[c];
+            out.s[3][c] += a0 * v2[c];
+            out.s[4][c] += dd0 * v[c];
+            out.s[5][c] += d0 * v1[c];
+            out.s[6][c] += d0 * v2[c];
+            out.s[7][c] += a0 * v11[c];
+            out.s[8][c] += a0 * v12[c];
+            out.s[9][c] += a0 * v22[c];
+        }
+    }
+}
+
+// u, grad u (if requested) and hess of particle p from the two halves of the
+// axis-0 sum.
+template <typename AT, int C>
+__device__ __forceinline__ void hess_store(const HessArgs& a, long p, const HessSums<AT, C>& lo,
+                                           const HessSums<AT, C>& hi) {
+    AT* u = static_cast<AT*>(a.u) + p * C;
+    AT* h = static_cast<AT*>(a.hess) + p * C * 6;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        u[c] = lo.s[0][c] + hi.s[0][c];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) h[6 * c + m] = lo.s[4 + m][c] + hi.s[4 + m][c];
+    }
+    if (a.grad) {
+        AT* g = static_cast<AT*>(a.grad) + p * C * 3;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g[3 * c + d] = lo.s[1 + d][c] + hi.s[1 + d][c];
+    }
+}
+
+template <typename AT, int C>
+__device__ __forceinline__ void hess_nan(const HessArgs& a, long p) {
+    const AT nan = AT(__builtin_nan(""));
+    AT* u = static_cast<AT*>(a.u) + p * C;
+    AT* h = static_cast<AT*>(a.hess) + p * C * 6;
+    for (int c = 0; c < C; ++c) u[c] = nan;
+    for (int c = 0; c < 6 * C; ++c) h[c] = nan;
+    if (a.grad) {
+        AT* g = static_cast<AT*>(a.grad) + p * C * 3;
+        for (int c = 0; c < 3 * C; ++c) g[c] = nan;
+    }
+}
+
+constexpr int HESS_TB = 64;   // threads per workgroup of the tiled kernel
+constexpr int HESS_TPG = 2;   // Morton tiles walked per workgroup
+
+// LDS-tiled variant: one one-wave workgroup per HESS_TPG consecutive Morton
+// tiles of 8^3 cells.  Each tile's (8+N-1)^3 block of the grid is copied into
+// LDS by the load unit's DMA path; then every particle of the tile reads its
+// stencil from LDS, two lanes per particle (one half of the axis-0 sum each,
+// combined with a lane shuffle) when the tile holds at most 32 particles.
+template <int N, typename CT, int C>
+__global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
+    using AT = typename Acc<CT>::type;
+    using G = TileGeom<N, CT, C, 8>;
+    constexpr int PERB = (G::SLOTS + HESS_TB - 1) / HESS_TB;
+    __shared__ u32x4 lds[G::SLOTS];
+    const CT* tile = reinterpret_cast<const CT*>(lds);
+    const int tid = threadIdx.x;
+    const uint32_t b0 = blockIdx.x * uint32_t(HESS_TPG);
+    const uint32_t b1 = min(b0 + uint32_t(HESS_TPG), a.nbf + 1);
+    for (uint32_t cur = b0; cur < b1; ++cur) {
+        // wave-uniform values steer every loop that holds a barrier
+        const uint32_t count = __builtin_amdgcn_readfirstlane(a.hist[cur]);
+        const uint32_t start = __builtin_amdgcn_readfirstlane(a.offs[cur]);
+        if (count == 0) continue;
+        if (cur == a.nbf) {
+            for (uint32_t j = tid; j < count; j += HESS_TB) hess_nan<AT, C>(a, long(a.perm[start + j]));
+            if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
+            continue;
+        }
+        const int o0 = int(compact3(cur >> 2)) * 8;
+        const int o1 = int(compact3(cur >> 1)) * 8;
+        const int o2 = int(compact3(cur)) * 8;
+        {
+            // the block's 16-byte slots, global -> LDS, all requested at once
+            const int lim0 = a.n0 + N - 1 - o0;
+            const int lim1 = a.n1 + N - 1 - o1;
+            const u32x4* gsrc = reinterpret_cast<const u32x4*>(static_cast<const CT*>(a.grid) +
+                                                              (long(o0) * a.P1 + o1) * a.pitch2 + long(o2) * C);
+            const int p1v = int(a.pitch2 / G::VEC);
+            const int p0v = a.P1 * p1v;
+#pragma unroll
+            for (int q = 0; q < PERB; ++q) {
+                const int sl = q * HESS_TB + tid;
+                const int row = sl / G::CH;
+                const int ch = sl - row * G::CH;
+                const int r0 = row / G::R1;
+                const int r1 = row - r0 * G::R1;
+                const bool ok = r0 < lim0 && r1 < lim1;
+                if (q < PERB - 1 || sl < G::SLOTS)
+                    __builtin_amdgcn_global_load_lds(
+                        (global_u32x4*)(gsrc + (ok ? r0 * p0v + r1 * p1v + ch : 0)),
+                        (__attribute__((address_space(3))) void*)(lds + q * HESS_TB), 16, 0, 0);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+        lds_barrier();
+        const bool pair = count <= uint32_t(HESS_TB / 2);
+        const int stride = pair ? HESS_TB / 2 : HESS_TB;
+        const uint32_t jlane = pair ? uint32_t(tid >> 1) : uint32_t(tid);
+        const int half = pair ? (tid & 1) : 0;
+        for (uint32_t j0 = 0; j0 < count; j0 += uint32_t(stride)) {
+            const uint32_t jj = j0 + jlane;
+            const bool active = jj < count;
+            const uint32_t slot = start + (active ? jj : 0u);
+            const long p = long(a.perm[slot]);
+            const double x[3] = {a.pos_sorted[3 * long(slot)], a.pos_sorted[3 * long(slot) + 1],
+                                 a.pos_sorted[3 * long(slot) + 2]};
+            int cell[3];
+            AT w[3][N], wd[3][N], wdd[3][N];
+            hess_setup<N, AT>(a, x, cell, w, wd, wdd);  // finite by construction of the tile
+            const CT* base = tile + ((cell[0] - o0) * G::R1 + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * C;
+            auto rows = [base](int ia, int ib) { return base + (ia * G::R1 + ib) * G::LROW; };
+            if (pair) {
+                const int ia0 = half * (N / 2);
+                AT w0s[N / 2], wd0s[N / 2], wdd0s[N / 2];
+#pragma unroll
+                for (int k = 0; k < N / 2; ++k) {
+                    w0s[k] = half ? w[0][N / 2 + k] : w[0][k];
+                    wd0s[k] = half ? wd[0][N / 2 + k] : wd[0][k];
+                    wdd0s[k] = half ? wdd[0][N / 2 + k] : wdd[0][k];
+                }
+                HessSums<AT, C> mine, other;
+                hess_planes<N, CT, AT, C, N / 2>(w0s, wd0s, wdd0s, w, wd, wdd,
+                                                 [&](int k, int ib) { return rows(ia0 + k, ib); }, mine);
+#pragma unroll
+                for (int m = 0; m < 10; ++m)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) other.s[m][c] = __shfl_xor(mine.s[m][c], 1, 64);
+                if (active && half == 0) hess_store<AT, C>(a, p, mine, other);
+            } else {
+                HessSums<AT, C> lo, hi;
+                hess_planes<N, CT, AT, C, N / 2>(w[0], wd[0], wdd[0], w, wd, wdd, rows, lo);
+                hess_planes<N, CT, AT, C, N / 2>(w[0] + N / 2, wd[0] + N / 2, wdd[0] + N / 2, w, wd, wdd,
+                                                 [&](int k, int ib) { return rows(N / 2 + k, ib); }, hi);
+                if (active) hess_store<AT, C>(a, p, lo, hi);
+            }
+        }
+        lds_barrier();
+    }
+}
+
+template <typename CT>
+bool hess_tiled_ok(int N, int C) {
+    // FP64 three-component order 6 spills registers in the tiled body: direct
+    if (sizeof(CT) == 8 && N == 6 && C == 3) return false;
+    auto ok = [](auto g) { return decltype(g)::BYTES <= 65536 && decltype(g)::ALIGNED; };
+    if (N == 4) return C == 1 ? ok(TileGeom<4, CT, 1, 8>{}) : ok(TileGeom<4, CT, 3, 8>{});
+    return C == 1 ? ok(TileGeom<6, CT, 1, 8>{}) : ok(TileGeom<6, CT, 3, 8>{});
+}
+
+template <typename CT>
+void launch_hess_tiled_ct(int N, int C, unsigned nb, hipStream_t s, const HessArgs& a) {
+    if (N == 4) {
+        if (C == 1) hipLaunchKernelGGL((k_gather_hess_tiled<4, CT, 1>), dim3(nb), dim3(HESS_TB), 0, s, a);
+        else hipLaunchKernelGGL((k_gather_hess_tiled<4, CT, 3>), dim3(nb), dim3(HESS_TB), 0, s, a);
+    } else {
+        if (C == 1) hipLaunchKernelGGL((k_gather_hess_tiled<6, CT, 1>), dim3(nb), dim3(HESS_TB), 0, s, a);
+        else hipLaunchKernelGGL((k_gather_hess_tiled<6, CT, 3>), dim3(nb), dim3(HESS_TB), 0, s, a);
+    }
+}
+
 template <typename CT>
 void launch_hess_ct(int N, int C, unsigned nb, hipStream_t s, const HessArgs& a) {
     if (N == 4) {
@@ -213,6 +470,9 @@ bsi_status hessian_run(bsi_field* f, const double* pos, int64_t P, void* u, void
     a.grid = f->grid;
     a.pos_sorted = pos_sorted;
     a.perm = perm;
+    a.hist = reinterpret_cast<const uint32_t*>(w + l.hist);
+    a.offs = reinterpret_cast<const uint32_t*>(w + l.offs);
+    a.nbf = uint32_t(bin_bucket_count(f, tile));
     a.P = long(P);
     a.n0 = f->n[0];
     a.n1 = f->n[1];
@@ -226,12 +486,23 @@ bsi_status hessian_run(bsi_field* f, const double* pos, int64_t P, void* u, void
     a.grad = grad;
     a.hess = hess;
     a.nonfinite = f->counters;
-    const unsigned nb = unsigned((P + HESS_B - 1) / HESS_B);
+    const int coef = f->desc.coef;
+    const bool tiled = tile == 8 && (coef == BSI_F64   ? hess_tiled_ok<double>(f->N, f->C)
+                                     : coef == BSI_F32 ? hess_tiled_ok<float>(f->N, f->C)
+                                                       : hess_tiled_ok<uint16_t>(f->N, f->C));
     {
         StageTimer tm(f->ctx, "gather_hess", s);
-        if (f->desc.coef == BSI_F64) launch_hess_ct<double>(f->N, f->C, nb, s, a);
-        else if (f->desc.coef == BSI_F32) launch_hess_ct<float>(f->N, f->C, nb, s, a);
-        else launch_hess_ct<uint16_t>(f->N, f->C, nb, s, a);
+        if (tiled) {
+            const unsigned nb = unsigned((size_t(a.nbf) + 1 + HESS_TPG - 1) / HESS_TPG);
+            if (coef == BSI_F64) launch_hess_tiled_ct<double>(f->N, f->C, nb, s, a);
+            else if (coef == BSI_F32) launch_hess_tiled_ct<float>(f->N, f->C, nb, s, a);
+            else launch_hess_tiled_ct<uint16_t>(f->N, f->C, nb, s, a);
+        } else {
+            const unsigned nb = unsigned((P + HESS_B - 1) / HESS_B);
+            if (coef == BSI_F64) launch_hess_ct<double>(f->N, f->C, nb, s, a);
+            else if (coef == BSI_F32) launch_hess_ct<float>(f->N, f->C, nb, s, a);
+            else launch_hess_ct<uint16_t>(f->N, f->C, nb, s, a);
+        }
     }
     BSI_HIP(hipGetLastError());
     return BSI_OK;

@@ -20,7 +20,7 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
-@pytest.mark.parametrize("src", ["eval.hip", "batch.hip", "fft.hip"])
+@pytest.mark.parametrize("src", ["eval.hip", "hessian.hip", "batch.hip", "fft.hip"])
 def test_barriers_only_in_uniform_loops(src, tmp_path):
     asm = tmp_path / (src + ".s")
     cmd = [HIPCC, "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",

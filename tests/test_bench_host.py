@@ -106,3 +106,9 @@ def test_gather_fma_count():
     assert bench.gather_fma(4, 3) == 672 and bench.gather_fma(6, 3) == 1908
     assert bench.gather_fma(4, 1) == 2 * 64 + 9 * 16 + 16
     assert bench.FMA_PEAK_PER_S == pytest.approx(39.32e12, rel=1e-3)
+
+
+def test_hessian_fma_count():
+    # 3 FMAs per coefficient (w, w', w'' along axis 2), 6 per row, 10 per plane
+    assert bench.hessian_fma(6, 3) == 3 * 3 * 216 + 6 * 3 * 36 + 10 * 3 * 6 == 2772
+    assert bench.hessian_fma(4, 1) == 3 * 64 + 6 * 16 + 40
