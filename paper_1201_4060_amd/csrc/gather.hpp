@@ -695,8 +695,30 @@ __device__ __forceinline__ void contract_plane(AT w0k, AT wd0k, const AT (*w)[N]
     for (int ib = 0; ib < N; ++ib) {
         const auto* r = row(ib);
         CT raw[N * C];
+        if constexpr (sizeof(CT) == 2 && FENCE && (N * C) % 2 == 0) {
+            // BF16 rows in LDS start on 2-byte boundaries, and unaligned wide
+            // LDS reads are slow (35 % of the order-6 gather): aligned dword
+            // reads from the dword boundary at or below the row start, then a
+            // funnel shift by the row's misalignment (0 or 16 bits) per pair of
+            // values.  The N*C/2 + 1 dwords end at most 4 bytes past the row's
+            // values, inside the row's padding to whole 16-byte chunks for
+            // every tile geometry of the tiled gathers.
+            const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(r)) & 2u;
+            const uint32_t* d = reinterpret_cast<const uint32_t*>(r - (mis >> 1));
+            constexpr int ND = N * C / 2 + 1;
+            uint32_t dw[ND];
 #pragma unroll
-        for (int e = 0; e < N * C; ++e) raw[e] = r[e];
+            for (int k = 0; k < ND; ++k) dw[k] = d[k];
+#pragma unroll
+            for (int k = 0; k < N * C / 2; ++k) {
+                const uint32_t v = __builtin_amdgcn_alignbit(dw[k + 1], dw[k], mis * 8u);
+                raw[2 * k] = CT(v & 0xffffu);
+                raw[2 * k + 1] = CT(v >> 16);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < N * C; ++e) raw[e] = r[e];
+        }
         AT tr[C], trd[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) tr[c] = trd[c] = AT(0);
@@ -880,6 +902,17 @@ __device__ __forceinline__ void direct_eval(const GatherArgs& a, long j, bool st
     }
 }
 
+// The aligned dword reads of a BF16 row (contract_plane) stay inside the row's
+// LDS pitch for every stencil start dc = 0 .. T2-1 of a T2-cell box.
+template <int N, int C, int T2, int LROW>
+constexpr bool bf16_rows_fit() {
+    for (int dc = 0; dc < T2; ++dc) {
+        const int start = 2 * dc * C;
+        if (start - start % 4 + 4 * (N * C / 2 + 1) > 2 * LROW) return false;
+    }
+    return true;
+}
+
 // LDS bytes one workgroup of B threads needs for the block geometry G: the
 // block itself (lanes past its last slot load nothing), so that as many blocks
 // as possible fit a CU (six of 27 KB for order 6 with 8^3 tiles).
@@ -906,6 +939,8 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
                                                  uint32_t start, u32x4* lds) {
     using AT = typename Acc<CT>::type;
     constexpr int PERB = (G::SLOTS + B - 1) / B;
+    static_assert(sizeof(CT) != 2 || bf16_rows_fit<N, C, G::R2 - N + 1, G::LROW>(),
+                  "BF16 row reads would leave the LDS row");
     const CT* tile = reinterpret_cast<const CT*>(lds);
     const int tid = threadIdx.x;
     const bool pair = count <= uint32_t(B / 2);
