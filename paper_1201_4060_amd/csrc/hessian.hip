@@ -243,6 +243,29 @@ __device__ __forceinline__ void hess_planes(const AT* w0, const AT* wd0, const A
 #pragma unroll
         for (int ib = 0; ib < N; ++ib) {
             const CT* r = row(k, ib);
+            CT raw[N * C];
+            if constexpr (sizeof(CT) == 2 && (N * C) % 2 == 0) {
+                // BF16 rows start on 2-byte boundaries: aligned dword reads and
+                // a funnel shift by the misalignment, as in the gather
+                typedef const __attribute__((address_space(3))) uint16_t lds_u16;
+                typedef const __attribute__((address_space(3))) uint32_t lds_u32;
+                lds_u16* lr = (lds_u16*)(r);
+                const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(lr)) & 2u;
+                lds_u32* d = (lds_u32*)(lr - (mis >> 1));
+                constexpr int ND = N * C / 2 + 1;
+                uint32_t dw[ND];
+#pragma unroll
+                for (int q = 0; q < ND; ++q) dw[q] = d[q];
+#pragma unroll
+                for (int q = 0; q < N * C / 2; ++q) {
+                    const uint32_t v = __builtin_amdgcn_alignbit(dw[q + 1], dw[q], mis * 8u);
+                    raw[2 * q] = CT(v & 0xffffu);
+                    raw[2 * q + 1] = CT(v >> 16);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < N * C; ++e) raw[e] = r[e];
+            }
             AT tr[C], trd[C], trdd[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) tr[c] = trd[c] = trdd[c] = AT(0);
@@ -250,7 +273,7 @@ __device__ __forceinline__ void hess_planes(const AT* w0, const AT* wd0, const A
             for (int e = 0; e < N; ++e) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    const AT val = widen<CT, AT>(r[e * C + c]);
+                    const AT val = widen<CT, AT>(raw[e * C + c]);
                     tr[c] += w[2][e] * val;
                     trd[c] += wd[2][e] * val;
                     trdd[c] += wdd[2][e] * val;
@@ -331,6 +354,7 @@ __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
     using AT = typename Acc<CT>::type;
     using G = TileGeom<N, CT, C, 8>;
     constexpr int PERB = (G::SLOTS + HESS_TB - 1) / HESS_TB;
+    static_assert(sizeof(CT) != 2 || bf16_rows_fit<N, C, 8, G::LROW>(), "BF16 row reads would leave the LDS row");
     __shared__ u32x4 lds[G::SLOTS];
     const CT* tile = reinterpret_cast<const CT*>(lds);
     const int tid = threadIdx.x;
