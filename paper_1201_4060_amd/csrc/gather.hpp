@@ -849,24 +849,40 @@ __device__ __forceinline__ uint32_t next_tile(const GatherArgs& a, uint32_t b, u
     return b;
 }
 
-// Addressing of the LDS block with cell origin (o0, o1, o2) in the
-// ghost-padded grid.  Rows outside the padded grid (partial blocks only; never
-// read by a particle) load the block origin instead; chunks past a row's end
-// read the next row or the allocation's slack.
-template <int N, typename CT, int C, typename G>
-struct TileLoad {
-    const u32x4* g;
-    int p0v, p1v, lim0, lim1;
-
-    __device__ __forceinline__ TileLoad(const GatherArgs& a, int o0, int o1, int o2) {
-        lim0 = a.n0 + N - 1 - o0;
-        lim1 = a.n1 + N - 1 - o1;
-        g = reinterpret_cast<const u32x4*>(static_cast<const CT*>(a.grid) +
-                                           (long(o0) * a.P1 + o1) * long(a.pitch2) + long(o2) * C);
-        p1v = a.pitch2 / G::VEC;  // row pitch in chunks (offsets inside a block stay < 2^31)
-        p0v = a.P1 * p1v;
+// Requests the LDS copy of the block of geometry G with cell origin (o0, o1,
+// o2) in the ghost-padded grid (row pitch pitch2 elements, P1 rows per plane):
+// slots tid, tid + B, ... are copied global -> LDS by the DMA path of the load
+// unit (no registers hold the data), each wavefront's instruction q filling 64
+// consecutive 16-byte slots from its wave-uniform LDS base; only the last step
+// can reach past the block, and its lanes there are masked off.  Rows outside
+// the padded grid (partial blocks only; never read by a particle) load the
+// block origin instead; chunks past a row's end read the next row or the
+// allocation's slack.  Does not wait for the loads.
+template <int N, typename CT, int C, typename G, int B>
+__device__ __forceinline__ void block_dma(const CT* grid, int n0, int n1, int P1, long pitch2, int o0, int o1,
+                                          int o2, u32x4* lds) {
+    constexpr int PERB = (G::SLOTS + B - 1) / B;
+    const int tid = threadIdx.x;
+    const int lim0 = n0 + N - 1 - o0;
+    const int lim1 = n1 + N - 1 - o1;
+    const u32x4* g = reinterpret_cast<const u32x4*>(grid + (long(o0) * P1 + o1) * pitch2 + long(o2) * C);
+    const int p1v = int(pitch2 / G::VEC);  // row pitch in chunks (offsets inside a block stay < 2^31)
+    const int p0v = P1 * p1v;
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+#pragma unroll
+    for (int q = 0; q < PERB; ++q) {
+        const int sl = q * B + tid;
+        const int row = sl / G::CH;
+        const int ch = sl - row * G::CH;
+        const int r0 = row / G::R1;
+        const int r1 = row - r0 * G::R1;
+        const bool ok = r0 < lim0 && r1 < lim1;
+        if (q < PERB - 1 || sl < G::SLOTS)
+            __builtin_amdgcn_global_load_lds((global_u32x4*)(g + (ok ? r0 * p0v + r1 * p1v + ch : 0)),
+                                             (__attribute__((address_space(3))) void*)(lds + q * B + wbase),
+                                             16, 0, 0);
     }
-};
+}
 
 // One particle evaluated straight from the grid in global memory (the caches
 // provide the reuse between neighbouring binned particles).  j is the
@@ -938,7 +954,6 @@ template <int N, typename CT, int C, bool GRAD, typename G, int B>
 __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, int o1, int o2, uint32_t count,
                                                  uint32_t start, u32x4* lds) {
     using AT = typename Acc<CT>::type;
-    constexpr int PERB = (G::SLOTS + B - 1) / B;
     static_assert(sizeof(CT) != 2 || bf16_rows_fit<N, C, G::R2 - N + 1, G::LROW>(),
                   "BF16 row reads would leave the LDS row");
     const CT* tile = reinterpret_cast<const CT*>(lds);
@@ -970,27 +985,7 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
     // memory round trip serves both (4 % faster for order 6)
     fetch_round(0);
     {
-        // slots tid, tid + B, ... of the block, copied global -> LDS by the
-        // DMA path of the load unit (no registers hold the data): each
-        // wavefront's instruction q fills 64 consecutive 16-byte slots
-        // starting at its wave-uniform LDS base
-        TileLoad<N, CT, C, G> tl(a, o0, o1, o2);
-        const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
-#pragma unroll
-        for (int q = 0; q < PERB; ++q) {
-            const int sl = q * B + tid;
-            const int row = sl / G::CH;
-            const int ch = sl - row * G::CH;
-            const int r0 = row / G::R1;
-            const int r1 = row - r0 * G::R1;
-            const bool ok = r0 < tl.lim0 && r1 < tl.lim1;
-            // only the last step can reach past the block; its lanes there
-            // are masked off and write no LDS
-            if (q < PERB - 1 || sl < G::SLOTS)
-                __builtin_amdgcn_global_load_lds(
-                    (global_u32x4*)(tl.g + (ok ? r0 * tl.p0v + r1 * tl.p1v + ch : 0)),
-                    (__attribute__((address_space(3))) void*)(lds + q * B + wbase), 16, 0, 0);
-        }
+        block_dma<N, CT, C, G, B>(static_cast<const CT*>(a.grid), a.n0, a.n1, a.P1, long(a.pitch2), o0, o1, o2, lds);
         // the weights' arithmetic stays below every block load: the compiler
         // waits for all loads in flight before the first use of a position,
         // so arithmetic scheduled between the block loads would split them

@@ -353,7 +353,6 @@ template <int N, typename CT, int C>
 __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
     using AT = typename Acc<CT>::type;
     using G = TileGeom<N, CT, C, 8>;
-    constexpr int PERB = (G::SLOTS + HESS_TB - 1) / HESS_TB;
     static_assert(sizeof(CT) != 2 || bf16_rows_fit<N, C, 8, G::LROW>(), "BF16 row reads would leave the LDS row");
     __shared__ u32x4 lds[G::SLOTS];
     const CT* tile = reinterpret_cast<const CT*>(lds);
@@ -373,29 +372,9 @@ __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
         const int o0 = int(compact3(cur >> 2)) * 8;
         const int o1 = int(compact3(cur >> 1)) * 8;
         const int o2 = int(compact3(cur)) * 8;
-        {
-            // the block's 16-byte slots, global -> LDS, all requested at once
-            const int lim0 = a.n0 + N - 1 - o0;
-            const int lim1 = a.n1 + N - 1 - o1;
-            const u32x4* gsrc = reinterpret_cast<const u32x4*>(static_cast<const CT*>(a.grid) +
-                                                              (long(o0) * a.P1 + o1) * a.pitch2 + long(o2) * C);
-            const int p1v = int(a.pitch2 / G::VEC);
-            const int p0v = a.P1 * p1v;
-#pragma unroll
-            for (int q = 0; q < PERB; ++q) {
-                const int sl = q * HESS_TB + tid;
-                const int row = sl / G::CH;
-                const int ch = sl - row * G::CH;
-                const int r0 = row / G::R1;
-                const int r1 = row - r0 * G::R1;
-                const bool ok = r0 < lim0 && r1 < lim1;
-                if (q < PERB - 1 || sl < G::SLOTS)
-                    __builtin_amdgcn_global_load_lds(
-                        (global_u32x4*)(gsrc + (ok ? r0 * p0v + r1 * p1v + ch : 0)),
-                        (__attribute__((address_space(3))) void*)(lds + q * HESS_TB), 16, 0, 0);
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-        }
+        // the block's 16-byte slots, global -> LDS, all requested at once
+        block_dma<N, CT, C, G, HESS_TB>(static_cast<const CT*>(a.grid), a.n0, a.n1, a.P1, a.pitch2, o0, o1, o2, lds);
+        __builtin_amdgcn_s_waitcnt(0);
         lds_barrier();
         const bool pair = count <= uint32_t(HESS_TB / 2);
         const int stride = pair ? HESS_TB / 2 : HESS_TB;
