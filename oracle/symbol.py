@@ -16,6 +16,8 @@ evaluates those lattice sums by direct truncated summation; the HIP library
 evaluates them differently (finite cosine sums over B-spline samples), and the
 tests pin this truncated series to that closed form.
 """
+import functools
+
 import numpy as np
 
 INTERP = "interp"
@@ -47,6 +49,13 @@ def signed_kappa(n):
 
 def prefilter_constants(n, N, variant=L2OPT, terms=DEFAULT_TERMS):
     """c(k) for FFT indices k = 0..n-1 of an axis with n points (Section 7)."""
+    return _constants(int(n), int(N), variant, int(terms)).copy()
+
+
+@functools.lru_cache(maxsize=64)
+def _constants(n, N, variant, terms):
+    # a pure function of its arguments, kept so that repeated prefilters of
+    # the same grid size do not re-sum the lattice series
     kappa = signed_kappa(n)
     if variant == INTERP:
         return 1.0 / sinc_power_sum(kappa, N, terms)

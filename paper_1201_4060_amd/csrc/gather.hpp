@@ -684,8 +684,9 @@ struct Partial {
 };
 
 // One axis-0 plane: rows row(ib), ib < N, reduced along axis 2 then axis 1,
-// accumulated into out with the plane's axis-0 weights w0k, wd0k.
-template <int N, typename CT, typename AT, int C, bool GRAD, bool FENCE, typename PlaneRowFn>
+// accumulated into out with the plane's axis-0 weights w0k, wd0k (rows read
+// straight from global memory).
+template <int N, typename CT, typename AT, int C, bool GRAD, typename PlaneRowFn>
 __device__ __forceinline__ void contract_plane(AT w0k, AT wd0k, const AT (*w)[N], const AT (*wd)[N],
                                                PlaneRowFn row, Partial<AT, C>& out) {
     AT v[C], v1[C], v2[C];
@@ -693,32 +694,10 @@ __device__ __forceinline__ void contract_plane(AT w0k, AT wd0k, const AT (*w)[N]
     for (int c = 0; c < C; ++c) v[c] = v1[c] = v2[c] = AT(0);
 #pragma unroll
     for (int ib = 0; ib < N; ++ib) {
-        const auto* r = row(ib);
+        const CT* r = row(ib);
         CT raw[N * C];
-        if constexpr (sizeof(CT) == 2 && FENCE && (N * C) % 2 == 0) {
-            // BF16 rows in LDS start on 2-byte boundaries, and unaligned wide
-            // LDS reads are slow (35 % of the order-6 gather): aligned dword
-            // reads from the dword boundary at or below the row start, then a
-            // funnel shift by the row's misalignment (0 or 16 bits) per pair of
-            // values.  The N*C/2 + 1 dwords end at most 4 bytes past the row's
-            // values, inside the row's padding to whole 16-byte chunks for
-            // every tile geometry of the tiled gathers.
-            const uint32_t mis = uint32_t(reinterpret_cast<uintptr_t>(r)) & 2u;
-            const uint32_t* d = reinterpret_cast<const uint32_t*>(r - (mis >> 1));
-            constexpr int ND = N * C / 2 + 1;
-            uint32_t dw[ND];
 #pragma unroll
-            for (int k = 0; k < ND; ++k) dw[k] = d[k];
-#pragma unroll
-            for (int k = 0; k < N * C / 2; ++k) {
-                const uint32_t v = __builtin_amdgcn_alignbit(dw[k + 1], dw[k], mis * 8u);
-                raw[2 * k] = CT(v & 0xffffu);
-                raw[2 * k + 1] = CT(v >> 16);
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < N * C; ++e) raw[e] = r[e];
-        }
+        for (int e = 0; e < N * C; ++e) raw[e] = r[e];
         AT tr[C], trd[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) tr[c] = trd[c] = AT(0);
@@ -739,7 +718,6 @@ __device__ __forceinline__ void contract_plane(AT w0k, AT wd0k, const AT (*w)[N]
                 v2[c] += w[1][ib] * trd[c];
             }
         }
-        if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -752,32 +730,112 @@ __device__ __forceinline__ void contract_plane(AT w0k, AT wd0k, const AT (*w)[N]
     }
 }
 
+// Raw values of one stencil row (N points x C components along axis 2) held
+// in registers between their LDS read and their use.  BF16 rows in LDS start
+// on 2-byte boundaries, and unaligned wide LDS reads are slow: they are read
+// as aligned dwords from the dword boundary at or below the row start and
+// realigned by a funnel shift per pair of values when used.  The N*C/2 + 1
+// dwords end at most 4 bytes past the row's values, inside the row's padding
+// to whole 16-byte chunks for every tile geometry of the tiled gathers.
+template <int N, typename CT, int C>
+struct LdsRow {
+    CT raw[N * C];
+    __device__ __forceinline__ void load(const CT* r) {
+#pragma unroll
+        for (int e = 0; e < N * C; ++e) raw[e] = r[e];
+    }
+    __device__ __forceinline__ CT get(int e) const { return raw[e]; }
+};
+
+template <int N, int C>
+struct LdsRow<N, uint16_t, C> {
+    static_assert((N * C) % 2 == 0, "BF16 rows are read as pairs");
+    static constexpr int ND = N * C / 2 + 1;
+    uint32_t dw[ND];
+    uint32_t mis;  // the row's misalignment in bits: 0 or 16
+    __device__ __forceinline__ void load(const uint16_t* r) {
+        const uint32_t m = uint32_t(reinterpret_cast<uintptr_t>(r)) & 2u;
+        const uint32_t* d = reinterpret_cast<const uint32_t*>(r - (m >> 1));
+        mis = m * 8u;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) dw[k] = d[k];
+    }
+    __device__ __forceinline__ uint16_t get(int e) const {
+        const uint32_t v = __builtin_amdgcn_alignbit(dw[e / 2 + 1], dw[e / 2], mis);
+        return uint16_t((e & 1) ? (v >> 16) : (v & 0xffffu));
+    }
+};
+
 // NIA consecutive axis-0 planes: w0[k], wd0[k] are the axis-0 weights of
 // plane k and row(k, ib) its rows; accumulation order is k = 0..NIA-1.
-// FENCE (LDS-resident rows): planes run as a loop so that only one plane's
-// rows are live at a time; otherwise everything is unrolled.
+// FENCE (LDS-resident rows): the NIA*N rows are software-pipelined -- the
+// LDS reads of row r+1 are issued before the arithmetic of row r, and a
+// scheduling fence after each row keeps at most two rows in registers -- so
+// that the LDS latency of one row hides behind the FMAs of the previous one.
+// Otherwise (rows in global memory) everything is unrolled and left to the
+// compiler.  The arithmetic, and its order, is the same in both forms.
 template <int N, typename CT, typename AT, int C, bool GRAD, int NIA, bool FENCE = false, typename RowFn>
 __device__ __forceinline__ void contract_planes(const AT* w0, const AT* wd0, const AT (*w)[N],
                                                 const AT (*wd)[N], RowFn row, Partial<AT, C>& out) {
 #pragma unroll
     for (int c = 0; c < C; ++c) out.u[c] = out.g0[c] = out.g1[c] = out.g2[c] = AT(0);
     if constexpr (FENCE) {
-#pragma unroll 1
-        for (int k = 0; k < NIA; ++k) {
-            AT w0k = w0[0], wd0k = wd0[0];
+        LdsRow<N, CT, C> buf[2];
+        buf[0].load(row(0, 0));
 #pragma unroll
-            for (int q = 1; q < NIA; ++q) {
-                w0k = (k == q) ? w0[q] : w0k;
-                wd0k = (k == q) ? wd0[q] : wd0k;
+        for (int k = 0; k < NIA; ++k) {
+            AT v[C], v1[C], v2[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = v1[c] = v2[c] = AT(0);
+#pragma unroll
+            for (int ib = 0; ib < N; ++ib) {
+                const int r = k * N + ib;
+                if (r + 1 < NIA * N) buf[(r + 1) & 1].load(row((r + 1) / N, (r + 1) % N));
+                const LdsRow<N, CT, C>& cur = buf[r & 1];
+                AT tr[C], trd[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) tr[c] = trd[c] = AT(0);
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const AT val = widen<CT, AT>(cur.get(e * C + c));
+                        tr[c] += w[2][e] * val;
+                        if constexpr (GRAD) trd[c] += wd[2][e] * val;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    v[c] += w[1][ib] * tr[c];
+                    if constexpr (GRAD) {
+                        v1[c] += wd[1][ib] * tr[c];
+                        v2[c] += w[1][ib] * trd[c];
+                    }
+                }
+                // the row's arithmetic is pinned above the fence (the
+                // accumulators pass through an empty side-effecting asm);
+                // otherwise it may sink below later rows' reads
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    if constexpr (GRAD) asm volatile("" : "+v"(v[c]), "+v"(v1[c]), "+v"(v2[c]));
+                    else asm volatile("" : "+v"(v[c]));
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-            contract_plane<N, CT, AT, C, GRAD, true>(w0k, wd0k, w, wd, [&](int ib) { return row(k, ib); },
-                                                    out);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                out.u[c] += w0[k] * v[c];
+                if constexpr (GRAD) {
+                    out.g0[c] += wd0[k] * v[c];
+                    out.g1[c] += w0[k] * v1[c];
+                    out.g2[c] += w0[k] * v2[c];
+                }
+            }
         }
     } else {
 #pragma unroll
         for (int k = 0; k < NIA; ++k)
-            contract_plane<N, CT, AT, C, GRAD, false>(w0[k], wd0[k], w, wd,
-                                                     [&](int ib) { return row(k, ib); }, out);
+            contract_plane<N, CT, AT, C, GRAD>(w0[k], wd0[k], w, wd, [&](int ib) { return row(k, ib); }, out);
     }
 }
 

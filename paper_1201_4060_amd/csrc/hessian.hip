@@ -341,14 +341,19 @@ __device__ __forceinline__ void hess_nan(const HessArgs& a, long p) {
     }
 }
 
-constexpr int HESS_TB = 64;   // threads per workgroup of the tiled kernel
-constexpr int HESS_TPG = 2;   // Morton tiles walked per workgroup
+constexpr int HESS_TB = 64;      // threads per workgroup of the tiled kernel
+constexpr int HESS_TPG = 2;      // Morton tiles walked per workgroup
+constexpr int HESS_SLICES = 4;   // workgroups sharing the rounds of one crowded tile
 
-// LDS-tiled variant: one one-wave workgroup per HESS_TPG consecutive Morton
-// tiles of 8^3 cells.  Each tile's (8+N-1)^3 block of the grid is copied into
-// LDS by the load unit's DMA path; then every particle of the tile reads its
-// stencil from LDS, two lanes per particle (one half of the axis-0 sum each,
-// combined with a lane shuffle) when the tile holds at most 32 particles.
+// LDS-tiled variant: HESS_SLICES one-wave workgroups per HESS_TPG consecutive
+// Morton tiles of 8^3 cells.  A tile's particles are evaluated in rounds of
+// one wavefront; slice s of the tile group takes rounds s, s + HESS_SLICES, ...
+// so that a crowded tile (a dense cluster of particles) is spread over several
+// CUs, and a slice without a round of a tile skips that tile.  Each working
+// slice copies the tile's (8+N-1)^3 block of the grid into LDS by the load
+// unit's DMA path; then every particle reads its stencil from LDS, two lanes
+// per particle (one half of the axis-0 sum each, combined with a lane shuffle)
+// when the tile holds at most 32 particles.
 template <int N, typename CT, int C>
 __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
     using AT = typename Acc<CT>::type;
@@ -357,7 +362,8 @@ __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
     __shared__ u32x4 lds[G::SLOTS];
     const CT* tile = reinterpret_cast<const CT*>(lds);
     const int tid = threadIdx.x;
-    const uint32_t b0 = blockIdx.x * uint32_t(HESS_TPG);
+    const uint32_t slice = blockIdx.x % uint32_t(HESS_SLICES);
+    const uint32_t b0 = (blockIdx.x / uint32_t(HESS_SLICES)) * uint32_t(HESS_TPG);
     const uint32_t b1 = min(b0 + uint32_t(HESS_TPG), a.nbf + 1);
     for (uint32_t cur = b0; cur < b1; ++cur) {
         // wave-uniform values steer every loop that holds a barrier
@@ -365,10 +371,16 @@ __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
         const uint32_t start = __builtin_amdgcn_readfirstlane(a.offs[cur]);
         if (count == 0) continue;
         if (cur == a.nbf) {
-            for (uint32_t j = tid; j < count; j += HESS_TB) hess_nan<AT, C>(a, long(a.perm[start + j]));
-            if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
+            if (slice == 0) {
+                for (uint32_t j = tid; j < count; j += HESS_TB) hess_nan<AT, C>(a, long(a.perm[start + j]));
+                if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
+            }
             continue;
         }
+        const bool pair = count <= uint32_t(HESS_TB / 2);
+        const int stride = pair ? HESS_TB / 2 : HESS_TB;
+        const uint32_t rounds = (count + uint32_t(stride) - 1) / uint32_t(stride);
+        if (slice >= rounds) continue;
         const int o0 = int(compact3(cur >> 2)) * 8;
         const int o1 = int(compact3(cur >> 1)) * 8;
         const int o2 = int(compact3(cur)) * 8;
@@ -376,11 +388,9 @@ __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
         block_dma<N, CT, C, G, HESS_TB>(static_cast<const CT*>(a.grid), a.n0, a.n1, a.P1, a.pitch2, o0, o1, o2, lds);
         __builtin_amdgcn_s_waitcnt(0);
         lds_barrier();
-        const bool pair = count <= uint32_t(HESS_TB / 2);
-        const int stride = pair ? HESS_TB / 2 : HESS_TB;
         const uint32_t jlane = pair ? uint32_t(tid >> 1) : uint32_t(tid);
         const int half = pair ? (tid & 1) : 0;
-        for (uint32_t j0 = 0; j0 < count; j0 += uint32_t(stride)) {
+        for (uint32_t j0 = slice * uint32_t(stride); j0 < count; j0 += uint32_t(stride) * HESS_SLICES) {
             const uint32_t jj = j0 + jlane;
             const bool active = jj < count;
             const uint32_t slot = start + (active ? jj : 0u);
@@ -496,7 +506,7 @@ bsi_status hessian_run(bsi_field* f, const double* pos, int64_t P, void* u, void
     {
         StageTimer tm(f->ctx, "gather_hess", s);
         if (tiled) {
-            const unsigned nb = unsigned((size_t(a.nbf) + 1 + HESS_TPG - 1) / HESS_TPG);
+            const unsigned nb = unsigned((size_t(a.nbf) + 1 + HESS_TPG - 1) / HESS_TPG) * HESS_SLICES;
             if (coef == BSI_F64) launch_hess_tiled_ct<double>(f->N, f->C, nb, s, a);
             else if (coef == BSI_F32) launch_hess_tiled_ct<float>(f->N, f->C, nb, s, a);
             else launch_hess_tiled_ct<uint16_t>(f->N, f->C, nb, s, a);

@@ -24,6 +24,8 @@ CASES = [
     (32, 1, 6, "f32"),
     (16, 3, 4, "bf16"),
     (36, 3, 6, "bf16"),
+    (32, 1, 4, "bf16"),
+    (32, 1, 6, "bf16"),
 ]
 
 

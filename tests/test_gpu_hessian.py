@@ -49,13 +49,18 @@ def test_hessian_f64(ctx, N, C):
 
 
 @pytest.mark.parametrize("coef", ["f32", "bf16"])
-def test_hessian_f32_bf16(ctx, coef):
+@pytest.mark.parametrize("N", [4, 6])
+@pytest.mark.parametrize("C", [1, 3])
+def test_hessian_f32_bf16(ctx, coef, N, C):
+    # 48^3 grid, 8000 uniform particles: about 37 per 8^3 tile, so tiles of
+    # at most 32 particles (two lanes per particle) and larger ones (one lane)
+    # both occur
     import paper_1201_4060_amd as bsi
     from oracle import prefilter, evaluate_hessian
-    n, C, N = 48, 3, 6
-    grid = prefilter(synth.kolmogorov_spectrum(n, C, seed=50), N)
+    n = 48
+    grid = prefilter(synth.kolmogorov_spectrum(n, C, seed=50 + C), N)
     stored = grid.astype(np.float32).astype(np.float64) if coef == "f32" else bf16_round(grid)
-    pos = _positions(8000, seed=51)
+    pos = _positions(8000, seed=51 + N)
     dt = bsi.BSI_F32 if coef == "f32" else bsi.BSI_BF16
     with bsi.Field(ctx, n, C, N, dt) as f:
         f.set_coefficients(dev(grid))
@@ -63,7 +68,7 @@ def test_hessian_f32_bf16(ctx, coef):
         u, g, h = host(u), host(g), host(h)
     wu, wg, wh = evaluate_hessian(stored, pos, N)
     eu, eg, eh = rel_err(u, wu), rel_err(g, wg), rel_err(h, wh)
-    log(f"  {coef} n={n}: max rel err u {eu.max():.2e} grad {eg.max():.2e} hess {eh.max():.2e}")
+    log(f"  {coef} n={n} C={C} N={N}: max rel err u {eu.max():.2e} grad {eg.max():.2e} hess {eh.max():.2e}")
     assert eu.max() < TOL_F32 and eg.max() < TOL_F32 and eh.max() < TOL_F32
 
 
@@ -88,13 +93,14 @@ def test_hessian_nonfinite_empty_and_no_grad(ctx):
         assert h0.shape == (0, C, 6)
 
 
-def test_hessian_full_size_sampled(ctx):
-    # 256^3 x3, FP32 grid, order 6, 10^6 uniform particles (the Hessian
+@pytest.mark.parametrize("N", [4, 6])
+def test_hessian_full_size_sampled(ctx, N):
+    # 256^3 x3, FP32 grid, orders 4 and 6, 10^6 uniform particles (the Hessian
     # benchmark's workload); the oracle on a sample of the particles
     import paper_1201_4060_amd as bsi
     from oracle import prefilter, evaluate_hessian
-    n, C, N = 256, 3, 6
-    log("hessian 256^3 x3 f32 N=6, 1e6 particles")
+    n, C = 256, 3
+    log(f"hessian 256^3 x3 f32 N={N}, 1e6 particles")
     uhat = synth.kolmogorov_spectrum(n, C, seed=1)
     grid = prefilter(uhat, N)
     pos = synth.uniform_positions(1_000_000, seed=101)
@@ -111,3 +117,32 @@ def test_hessian_full_size_sampled(ctx):
     # the field is divergence free: the trace of grad u is small (logged)
     div = g[:, 0, 0] + g[:, 1, 1] + g[:, 2, 2]
     log(f"  rms div / rms grad = {np.sqrt(np.mean(div ** 2) / np.mean(g ** 2)):.2e}")
+
+
+@pytest.mark.parametrize("coef", ["f64", "f32"])
+def test_hessian_crowded_tile(ctx, coef):
+    # one 8^3 tile holding 2e4 particles (a dense cluster) beside sparse ones
+    # and non-finite positions: the tile's rounds are shared by several
+    # workgroups; every particle against the oracle
+    import paper_1201_4060_amd as bsi
+    from oracle import prefilter, evaluate_hessian
+    n, C, N = 32, 3, 4
+    grid = prefilter(synth.kolmogorov_spectrum(n, C, seed=70), N)
+    rng = np.random.default_rng(71)
+    h = 2 * np.pi / n
+    crowd = (np.array([8.0, 16.0, 0.0]) + rng.uniform(0, 8, size=(20000, 3))) * h
+    pos = np.concatenate([crowd, synth.uniform_positions(3000, seed=72), [[np.nan, 1.0, 2.0]]])
+    pos = pos[rng.permutation(pos.shape[0])]
+    stored = grid if coef == "f64" else grid.astype(np.float32).astype(np.float64)
+    dt = bsi.BSI_F64 if coef == "f64" else bsi.BSI_F32
+    tol = TOL_F64 if coef == "f64" else TOL_F32
+    with bsi.Field(ctx, n, C, N, dt) as f:
+        f.set_coefficients(dev(grid))
+        u, g, hs = f.eval_hessian(dev(pos))
+        u, g, hs = host(u), host(g), host(hs)
+    ok = np.isfinite(pos).all(axis=1)
+    assert np.isnan(u[~ok]).all() and np.isnan(hs[~ok]).all()
+    wu, wg, wh = evaluate_hessian(stored, pos[ok], N)
+    eu, eg, eh = rel_err(u[ok], wu), rel_err(g[ok], wg), rel_err(hs[ok], wh)
+    log(f"  crowded {coef}: max rel err u {eu.max():.2e} grad {eg.max():.2e} hess {eh.max():.2e}")
+    assert eu.max() < tol and eg.max() < tol and eh.max() < tol

@@ -2,9 +2,9 @@
 
 Requests of varying size against several resident fields are submitted while
 others run; each result must be bitwise the stand-alone bsi_eval_ex result of
-its field with the configuration the context picks for its size (the paper's
-arithmetic is unchanged by serving, so parity with the oracle is inherited from
-the single-field tests).  Admission must respect the device-memory budget.
+its field with the configuration the context picks for its size, and served
+results on 256^3 fields are also compared with the FP64 oracle directly.
+Admission must respect the device-memory budget.
 """
 import threading
 
@@ -203,6 +203,65 @@ def test_served_full_size(served):
             assert np.array_equal(u.numpy(), host(ua)) and np.array_equal(g.numpy(), host(ga)), \
                 f"request {k} (field {fid}, P={P}) differs from its stand-alone result"
             log(f"  request {k}: field {fid}, P={P}: bitwise equal to stand-alone")
+    finally:
+        for f in fields.values():
+            f.close()
+
+
+def test_served_requests_match_oracle(served):
+    """Served requests against the FP64 oracle (Section 7 prefilter of the same
+    spectrum, then the plain stencil sum): 256^3 x3 FP32 fields of both orders,
+    uniform and clustered requests served while others run; every sampled
+    output within 1e-5 of the oracle per quantity."""
+    import torch
+    import paper_1201_4060_amd as bsi
+    from oracle import prefilter, evaluate
+    from gpu_common import rel_err, TOL_F32
+    ctx, _ = served
+    n, C = 256, 3
+    uhat = synth.kolmogorov_spectrum(n, C, seed=510)
+    fields = {}
+    try:
+        spec = dev(uhat)
+        for fid, N in enumerate((4, 6)):
+            f = bsi.Field(ctx, n, C, N, bsi.BSI_F32)
+            f.set_spectrum(spec)
+            fields[fid] = f
+        del spec
+        torch.cuda.synchronize()
+        reqs = []
+        for k, (fid, P, clustered) in enumerate(((0, 60_000, False), (1, 40_000, True), (1, 5_000, False),
+                                                (0, 30_000, True), (1, 80_000, False), (0, 2_000, True))):
+            pos = synth.clustered_positions(P // 2, 3, P // 6, 0.1, seed=640 + k) if clustered else \
+                synth.uniform_positions(P, seed=640 + k)
+            pos = pos[:P]
+            p = _pinned((pos.shape[0], 3), torch.float64)
+            p.numpy()[:] = pos
+            u = _pinned((pos.shape[0], C), torch.float32)
+            g = _pinned((pos.shape[0], C, 3), torch.float32)
+            u.fill_(float("nan"))
+            g.fill_(float("nan"))
+            reqs.append((fid, p, u, g))
+        with bsi.Server(ctx, hbm_budget=256 << 20, max_slots=4) as sv:
+            for fid, f in fields.items():
+                sv.add_field(fid, f)
+            tickets = [sv.submit(fid, p, u, g) for fid, p, u, g in reqs]
+            for t in tickets:
+                sv.wait(t)
+            st = sv.stats()
+            assert st["completed"] == len(reqs) and st["failed"] == 0
+            log(f"  served {len(reqs)} requests on 256^3 fields, max in flight {st['max_inflight']}")
+        grids = {fid: prefilter(uhat, N) for fid, N in enumerate((4, 6))}
+        rng = np.random.default_rng(12)
+        for k, (fid, p, u, g) in enumerate(reqs):
+            N = (4, 6)[fid]
+            P = p.shape[0]
+            pick = np.sort(rng.choice(P, size=min(P, 1500), replace=False))
+            wu, wg = evaluate(grids[fid], p.numpy()[pick], N)
+            eu = rel_err(u.numpy()[pick], wu).max()
+            eg = rel_err(g.numpy()[pick], wg).max()
+            log(f"  request {k}: order {N}, P={P}: max rel err u {eu:.2e} grad {eg:.2e}")
+            assert eu < TOL_F32 and eg < TOL_F32, (k, eu, eg)
     finally:
         for f in fields.values():
             f.close()
