@@ -1,23 +1,26 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the B-spline interpolation hot path on one MI355X.
 
-Default workload (--form plain): a 256^3 three-component divergence-free
+Default workload (--form precision): a 512^3 three-component divergence-free
 Kolmogorov field (spectrum |uhat|^2 ~ k^-11/3, cut-off |k| <= n/3, complex128
-input), FP32 coefficient grid, spline orders 4 and 6, 10^6 uniform particles.
-One step runs the whole path for each order: prefilter (FP64 symbol multiply +
-inverse 3D real FFT) then evaluation (cell/Morton binning + gather) of u and
-grad u at every particle.  value = interpolated points (particles x orders)
-per second of whole step, inputs resident in HBM.
+input), spline order 6, 10^7 clustered particles (half uniform, half in 100
+Gaussian blobs, sigma 0.1).  One step runs the whole path on the FP32
+coefficient grid: prefilter (FP64 symbol multiply + inverse 3D real FFT), then
+evaluation (cell/Morton binning + gather) of u and grad u at every particle.
+value = particles per second of whole step, inputs resident in HBM.  The same
+step on the BF16 grid and on the plain FP64 grid is timed on the same inputs
+(legs), every path's error against the FP64 oracle is reported, and the serving
+form's latency percentiles are attached.
 
 Other forms (one JSON line each, same keys):
-  --form precision  512^3 x3 field, order 6, FP32 and BF16 grids, 10^7
-                    clustered particles; errors against the FP64 oracle
+  --form plain      256^3 x3 field, FP32 grid, orders 4 and 6, 10^6 uniform
+                    particles; step = prefilter + eval per order
   --form batch      64 fields (n in {64,128,192,256}, order 4|6, 10^3..10^6
                     particles each) in one persistent gather launch replayed
                     from a HIP graph; beside it one launch per field
   --form serve      resident 1024^3 and 256^3 fields (both orders), Poisson
                     particle-query requests; points/s with p50/p99 latency
-  --form hessian    the default workload with second derivatives as well
+  --form hessian    the plain workload with second derivatives as well
   --form copy       1 GiB device copy (calibrates HBM byte counters)
 
 Prints one JSON line on stdout; diagnostics go to stderr.
@@ -109,15 +112,15 @@ def fft_bytes(stage, n, C, order, spec_bytes=16, work_bytes=8, grid_bytes=4):
     return None
 
 
-def measured_traffic(key):
-    """HBM bytes per launch of stage `key` from the committed counter summary.
+def measured_traffic(key, path=None):
+    """HBM bytes per launch of stage `key` from a committed counter summary.
 
     The summary records FETCH_SIZE + WRITE_SIZE (scaled by a plain copy of
     known size) with a hash of the kernel's sources; the figure is returned
     only while the sources still hash the same, else None.
     """
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path or TRAFFIC_FILE).read()
     except OSError:
         return None
     line = next((ln for ln in text.splitlines() if ln.startswith("traffic-json:")), None)
@@ -517,87 +520,188 @@ def form_hessian(args):
 
 # -------------------------------------------------------- precision form ---
 
-def form_precision(args):
-    """512^3 x3 field, order 6, FP32 and BF16 coefficient grids, 10^7 clustered
-    particles (5e6 uniform + 100 Gaussian blobs of 5e4, sigma 0.1)."""
-    import torch
+PREC_N, PREC_C, PREC_ORDER, PREC_P = 512, 3, 6, 10_000_000
+PREC_FIELD_SEED, PREC_POS_SEED = 2, 102
+PREC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_512cube_x3_order6_1e7_clustered.md")
+
+
+def _oracle_component_prefilter(args):
+    # one component of the FP64 prefilter, written into shared memory
+    from multiprocessing import shared_memory
+    import oracle
+    shm_name, c, N, shape = args
+    uhat = _CPU_SHARED["uhat"]
+    t0 = time.perf_counter()
+    g = oracle.prefilter(uhat[c:c + 1], N)[0]
+    t1 = time.perf_counter()
+    shm = shared_memory.SharedMemory(name=shm_name)
+    out = np.ndarray(shape, dtype=np.float64, buffer=shm.buf)
+    out[c] = g
+    del out
+    shm.close()
+    return t1 - t0
+
+
+def _oracle_eval_chunk(args):
+    import oracle
+    lo, hi, N = args
+    t0 = time.perf_counter()
+    oracle.evaluate(_CPU_SHARED["grid"], _CPU_SHARED["pos"][lo:hi], N)
+    return time.perf_counter() - t0
+
+
+_CPU_SHARED = {}
+
+
+def cpu_baseline_all_cores(uhat, pos, N, P_total, per_worker, workers, label):
+    """The FP64 oracle as it stands, timed on the host's cores: its prefilter
+    with one process per field component, then its evaluation of a bounded
+    particle sample split over `workers` processes (fork; each numpy call
+    single-threaded); the sample's rate is scaled to the whole particle set.
+    Also reports the same work on one thread (component prefilter times summed,
+    a smaller sample evaluated alone)."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
     from threadpoolctl import threadpool_limits
+    import oracle
+    C = uhat.shape[0]
+    n = uhat.shape[1]
+    shape = (C, n, n, n)
+    shm = shared_memory.SharedMemory(create=True, size=int(np.prod(shape)) * 8)
+    try:
+        _CPU_SHARED["uhat"] = uhat
+        ctx = mp.get_context("fork")
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            with ctx.Pool(C) as pool:
+                comp_times = pool.map(_oracle_component_prefilter, [(shm.name, c, N, shape) for c in range(C)])
+            t_pf = time.perf_counter() - t0
+            grid = np.ndarray(shape, dtype=np.float64, buffer=shm.buf)
+            rng = np.random.default_rng(0)
+            sample = np.sort(rng.choice(pos.shape[0], per_worker * workers, replace=False))
+            _CPU_SHARED["grid"] = grid
+            _CPU_SHARED["pos"] = np.ascontiguousarray(pos[sample])
+            chunks = [(w * per_worker, (w + 1) * per_worker, N) for w in range(workers)]
+            t1 = time.perf_counter()
+            with ctx.Pool(workers) as pool:
+                pool.map(_oracle_eval_chunk, chunks)
+            t_ev = time.perf_counter() - t1
+            # one thread: a smaller sample evaluated in this process
+            one = min(per_worker, 20000)
+            t2 = time.perf_counter()
+            oracle.evaluate(grid, _CPU_SHARED["pos"][:one], N)
+            t_one = time.perf_counter() - t2
+            del grid
+    finally:
+        _CPU_SHARED.clear()
+        shm.close()
+        shm.unlink()
+    S = per_worker * workers
+    total = t_pf + t_ev * P_total / S
+    total_one = sum(comp_times) + t_one * P_total / one
+    try:
+        model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        model = "unknown"
+    eprint(f"cpu oracle: prefilter {t_pf:.2f} s on {C} processes (components {comp_times}), "
+           f"eval of {S} particles {t_ev:.2f} s on {workers} processes; one thread: eval {one} in {t_one:.2f} s")
+    return {"value": P_total / total, "unit": "points/s", "cores": max(workers, C), "kind": "oracle",
+            "sample": (f"FP64 oracle prefilter of the {label} field (one process per component, "
+                       f"{t_pf:.1f} s) + evaluation of {S} of the {P_total} particles on {workers} processes "
+                       f"({t_ev:.1f} s), scaled to all particles; numpy, one thread per process"),
+            "host": {"nproc": os.cpu_count(), "model": model},
+            "one_thread": {"value": P_total / total_one, "unit": "points/s",
+                           "sample": f"component prefilters summed ({sum(comp_times):.1f} s) + {one} particles "
+                                     f"evaluated on one thread ({t_one:.2f} s), scaled"}}
+
+
+def form_precision(args):
+    """512^3 x3 divergence-free field, order 6, 10^7 clustered particles (5e6
+    uniform + 100 Gaussian blobs of 5e4, sigma 0.1).  The headline step is the
+    FP32-grid path (prefilter + binning + gather); the BF16-grid path and the
+    plain FP64-grid path run the same step on the same inputs, timed apart;
+    every path's error against the FP64 oracle is reported on a sample."""
+    import torch
     import synth
     import oracle
     import paper_1201_4060_amd as bsi
-    n, C, N, Pp = 512, 3, 6, 10_000_000
-    dev = torch.device("cuda:0")
+    n, C, N, Pp = PREC_N, PREC_C, PREC_ORDER, PREC_P
     eprint("generating the 512^3 spectrum and 1e7 clustered particles ...")
-    uhat_np = synth.kolmogorov_spectrum(n, C, seed=2)
-    pos_np = synth.clustered_positions(5_000_000, 100, 50_000, 0.1, seed=102)
+    uhat_np = synth.kolmogorov_spectrum(n, C, seed=PREC_FIELD_SEED)
+    pos_np = synth.clustered_positions(5_000_000, 100, 50_000, 0.1, seed=PREC_POS_SEED)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the oracle's worker processes are forked
+        eprint("timing the CPU oracle on the host's cores ...")
+        workers = max(1, min(args.cpu_workers, os.cpu_count() or 1))
+        cpu = cpu_baseline_all_cores(uhat_np, pos_np, N, Pp, args.cpu_per_worker, workers, "512^3x3")
+    dev = torch.device("cuda:0")
+    kinds = (("f32", bsi.BSI_F32, 4), ("bf16", bsi.BSI_BF16, 2), ("f64", bsi.BSI_F64, 8))
+    ctxs = {k: bsi.Context(0) for k, _, _ in kinds}
     uhat = torch.from_numpy(uhat_np).to(dev)
     pos = torch.from_numpy(pos_np).to(dev)
-    kinds = (("f32", bsi.BSI_F32, 4), ("bf16", bsi.BSI_BF16, 2))
-    ctxs = {k: bsi.Context(0) for k, _, _ in kinds}
     fields = {k: bsi.Field(ctxs[k], n, C, N, dt) for k, dt, _ in kinds}
-    outs = {k: (torch.empty((Pp, C), dtype=torch.float32, device=dev),
-                torch.empty((Pp, C, 3), dtype=torch.float32, device=dev)) for k, _, _ in kinds}
+    outs = {k: (torch.empty((Pp, C), dtype=fields[k].out_dtype, device=dev),
+                torch.empty((Pp, C, 3), dtype=fields[k].out_dtype, device=dev)) for k, _, _ in kinds}
 
-    def kind_part(k):
+    def part(k):
         def run():
             fields[k].set_spectrum(uhat)
             fields[k].eval(pos, out=outs[k])
         return run
 
-    def step_one_stream():
-        for k, _, _ in kinds:
-            kind_part(k)()
-
-    # the two grid types are independent: with --streams 2 they run on two streams
-    sides = [torch.cuda.Stream() for _ in kinds[1:]]
-    parts = [kind_part(k) for k, _, _ in kinds]
-
-    def step():
-        if args.streams > 1:
-            overlapped(parts, sides)
-        else:
-            step_one_stream()
-
-    sps = timed_steps(step, args.warmup, args.steps, list(ctxs.values()), bsi, stage_timing=False)
-    pct = dict(STEP_PERCENTILES)
-    sps_one = sps if args.streams == 1 else timed_steps(step_one_stream, 1, args.steps, list(ctxs.values()),
-                                                         bsi, stage_timing=False)
-    sps_inst = timed_steps(step_one_stream, 1, args.steps, list(ctxs.values()), bsi)
-    STEP_PERCENTILES.clear()
-    STEP_PERCENTILES.update(pct)
-    eprint(f"{sps * 1e3:.3f} ms/step on {args.streams} stream(s), {sps_one * 1e3:.3f} on one stream, "
-           f"{sps_inst * 1e3:.3f} on one stream with stage events")
-    stages = {}
+    sps, pct, stages = {}, {}, {}
     for k, _, _ in kinds:
+        steps = args.steps if k != "f64" else max(2, args.steps // 2)
+        sps[k] = timed_steps(part(k), args.warmup, steps, [ctxs[k]], bsi, stage_timing=False)
+        pct[k] = dict(STEP_PERCENTILES)
+        timed_steps(part(k), 1, steps, [ctxs[k]], bsi)   # the same steps with the library's stage events
         stages.update(read_stages(bsi, ctxs[k], k))
         bsi._bsi.bsi_ctx_set_timing(ctxs[k].handle, False)
-    print_stages(stages, sps_inst, args.steps)
+        eprint(f"{k}: {sps[k] * 1e3:.3f} ms/step")
+    STEP_PERCENTILES.clear()
+    STEP_PERCENTILES.update(pct["f32"])
+    print_stages({s: v for s, v in stages.items() if s.endswith("@f32")}, sps["f32"], args.steps)
+    copy_gbs = copy_bandwidth()
     U = distinct_stencil_points(pos, n, N)
     cbytes = {k: cb for k, _, cb in kinds}
+    obytes = {"f32": 4, "bf16": 4, "f64": 8}
     alg = {}
     for key in stages:
         st, k = key.split("@")
-        alg[key] = gather_bytes(Pp, C, U, cbytes[k]) if st == "gather" else fft_bytes(st, n, C, N)
-    dom = max((k for k in stages if alg[k] is not None), key=lambda k: stages[k]["total_ms"])
-    roofline = roofline_entry(dom, alg[dom], stages[dom]["avg_us"])
-    per = {}
-    for k, _, cb in kinds:
-        g = stages[f"gather@{k}"]
-        e = roofline_entry(f"gather@{k}", alg[f"gather@{k}"], g["avg_us"])
-        per[k] = {"gather_us": e["avg_us"], "gather_achieved_GBs": e["achieved"], "gather_frac": e["frac"],
-                  "gather_points_per_s": round(Pp / (g["avg_us"] * 1e-6), 1),
-                  "gather_alu_frac": round(Pp * gather_fma(N, C) / (g["avg_us"] * 1e-6) / FMA_PEAK_PER_S, 4),
-                  "grid_bytes": fields[k].nbytes()}
-    # errors against the FP64 oracle on a sample (outside the timed region);
-    # the same oracle work is the CPU baseline
+        if st == "gather":
+            alg[key] = gather_bytes(Pp, C, U, cbytes[k], obytes[k])
+        else:
+            alg[key] = fft_bytes(st, n, C, N, grid_bytes=cbytes[k], work_bytes=16 if k == "f64" else 8)
+    fma_peak = {"f32": FMA_PEAK_PER_S, "bf16": FMA_PEAK_PER_S, "f64": FMA_PEAK_PER_S / 2}
+
+    def gather_entry(k):
+        key = f"gather@{k}"
+        e = roofline_entry(key, alg[key], stages[key]["avg_us"], measured_traffic(key, PREC_TRAFFIC_FILE))
+        fma_s = Pp * gather_fma(N, C) / (stages[key]["avg_us"] * 1e-6)
+        e["frac_of_copy"] = round(e["achieved"] / copy_gbs, 4)
+        e["alu"] = {"fma_per_particle": gather_fma(N, C), "achieved_TFMA_s": round(fma_s / 1e12, 3),
+                    "peak_TFMA_s": round(fma_peak[k] / 1e12, 3), "frac": round(fma_s / fma_peak[k], 4)}
+        e["points_per_s"] = round(Pp / (stages[key]["avg_us"] * 1e-6), 1)
+        return e
+
+    roofline = gather_entry("f32")
+    legs = {}
+    for k, _, _ in kinds:
+        ev = sum(stages[f"{st}@{k}"]["avg_us"] for st in ("bin_count", "bin_scan", "bin_scatter", "gather"))
+        pf = sum(stages[f"{st}@{k}"]["avg_us"] for st in ("fft_axis0", "fft_axis1", "fft_c2r"))
+        legs[k] = {"points_per_s": round(Pp / sps[k], 1), "ms_per_step": round(sps[k] * 1e3, 4),
+                   "ms_per_step_percentiles": pct[k], "prefilter_us": round(pf, 1), "eval_us": round(ev, 1),
+                   "eval_points_per_s": round(Pp / (ev * 1e-6), 1), "grid_bytes": fields[k].nbytes(),
+                   "gather": gather_entry(k) if k != "f32" else "see roofline",
+                   "stages_us": {s.split("@")[0]: round(v["avg_us"], 2) for s, v in stages.items()
+                                 if s.endswith("@" + k)}}
+    # errors of every path against the FP64 oracle on a particle sample
+    # (outside the timed region); the oracle's grid comes from its own prefilter
     eprint("FP64 oracle on a sample ...")
     sample = np.sort(np.random.default_rng(1).choice(Pp, args.cpu_sample_precision, replace=False))
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        grid = oracle.prefilter(uhat_np, N)
-        t1 = time.perf_counter()
-        want_u, want_g = oracle.evaluate(grid, pos_np[sample], N)
-        t2 = time.perf_counter()
+    grid = oracle.prefilter(uhat_np, N)
+    want_u, want_g = oracle.evaluate(grid, pos_np[sample], N)
     umax = float(np.abs(grid).max())
     del grid
     S6 = 115.0 / 96.0  # max_t sum_j |w'_j(t)| of the order-6 derivative weights
@@ -621,24 +725,23 @@ def form_precision(args):
             errs["bound_grad_abs"] = 2.0 ** -8 * umax * S6 * n / (2 * np.pi)
             errs["max_abs_u"] = float(np.abs(u - want_u).max())
             errs["max_abs_grad"] = float(np.abs(g - want_g).max())
-        per[k]["error_vs_fp64_oracle"] = errs
+        legs[k]["error_vs_fp64_oracle"] = errs
         eprint(f"  {k}: {json.dumps(errs)}")
-    cpu = {"value": Pp / ((t1 - t0) + (t2 - t1) * Pp / len(sample)), "unit": "points/s", "cores": 1,
-           "kind": "oracle",
-           "sample": (f"FP64 prefilter of the 512^3x3 field ({t1 - t0:.1f} s) + evaluation of "
-                      f"{len(sample)} of the 1e7 particles ({t2 - t1:.1f} s), scaled to 1e7 particles "
-                      f"for one grid; numpy, one thread")}
     for k, _, _ in kinds:
         fields[k].close()
         ctxs[k].close()
-    config = {"workload": "512^3 x3 divergence-free Kolmogorov field, order 6, FP32 and BF16 coefficient "
-                          "grids (FP32 accumulation), 1e7 clustered particles (5e6 uniform + 100 Gaussian "
-                          "blobs sigma 0.1); step = prefilter + eval per grid type",
-              "n": n, "ncomp": C, "order": N, "particles": Pp, "grid_dtypes": ["f32", "bf16"],
+    del outs, uhat, pos, uhat_np
+    torch.cuda.empty_cache()
+    config = {"workload": "512^3 x3 divergence-free Kolmogorov field, order 6, 1e7 clustered particles "
+                          "(5e6 uniform + 100 Gaussian blobs of 5e4, sigma 0.1); step = prefilter (FP64 symbol "
+                          "multiply + inverse 3D real FFT) + binning + gather of u and grad u; headline: FP32 "
+                          "coefficient grid; the BF16-grid and FP64-grid paths timed on the same inputs",
+              "n": n, "ncomp": C, "order": N, "particles": Pp, "grid_dtype": "f32", "spectrum_dtype": "c128",
               "parallelism": "single GPU"}
-    return base_line(args, 2 * Pp / sps, "points/s", sps, "f32", config, roofline, cpu, per_grid_dtype=per,
-                     streams=args.streams, ms_per_step_one_stream=round(sps_one * 1e3, 4),
-                     stages_us={k: round(v["avg_us"], 2) for k, v in stages.items()})
+    extra = {"legs": legs, "copy_GBs": round(copy_gbs, 1)}
+    if args.serve_in_default:
+        extra["serving"] = serve_summary(args)
+    return base_line(args, Pp / sps["f32"], "points/s", sps["f32"], "f32", config, roofline, cpu, **extra)
 
 
 # ------------------------------------------------------------ batch form ---
@@ -766,7 +869,9 @@ def form_batch(args):
 
 # ------------------------------------------------------------ serve form ---
 
-def form_serve(args):
+def serve_run(args, nreq):
+    """Resident snapshots served to Poisson particle-query requests: the saturated
+    closed-loop rate R, then open loop at 0.5 R and 0.8 R (nreq requests each)."""
     import torch
     import synth
     import paper_1201_4060_amd as bsi
@@ -849,7 +954,7 @@ def form_serve(args):
     sv.reset_stats()
     eprint("closed loop (16 outstanding) ...")
     t0 = time.perf_counter()
-    sat = run(args.serve_requests, 1000, closed=16)
+    sat = run(nreq, 1000, closed=16)
     wall = time.perf_counter() - t0
     R = sat["completed"] / wall
     results = {"saturated": {"requests_per_s": round(R, 1), "points_per_s": round(sat["points_per_s"], 1),
@@ -859,7 +964,7 @@ def form_serve(args):
     for frac in (0.5, 0.8):
         sv.reset_stats()
         eprint(f"open loop at {frac} x saturated rate ...")
-        st = run(args.serve_requests, 100000 * int(10 * frac), rate=frac * R)
+        st = run(nreq, 100000 * int(10 * frac), rate=frac * R)
         results[f"rate_{frac}"] = {"rate_req_s": round(frac * R, 1), "points_per_s": round(st["points_per_s"], 1),
                                    "p50_ms": st["p50_ns"] / 1e6, "p99_ms": st["p99_ns"] / 1e6,
                                    "device_p50_ms": st["device_p50_ns"] / 1e6,
@@ -871,18 +976,35 @@ def form_serve(args):
     for fl in fields.values():
         fl.close()
     ctx.close()
-    main_rate = results["rate_0.8"]
     config = {"workload": f"{n_big} x {big_n}^3 + {n_small} x {small_n}^3 resident divergence-free Kolmogorov "
                           "snapshots, FP32 grids for orders 4 and 6; Poisson requests (snapshot uniform, order "
                           "uniform, 10^U(3,6) particles, half uniform / half clustered positions) from pinned "
                           "host memory; value at 0.8 x the saturated request rate",
-              "resident_GiB": round(resident / 2**30, 1), "requests_per_run": args.serve_requests,
+              "resident_GiB": round(resident / 2**30, 1), "requests_per_run": nreq,
               "slots": args.serve_slots, "hbm_budget_MiB": args.serve_budget, "parallelism": "single GPU"}
+    return results, config
+
+
+def form_serve(args):
+    results, config = serve_run(args, args.serve_requests)
+    main_rate = results["rate_0.8"]
     line = base_line(args, main_rate["points_per_s"], "points/s", 0.0, "f32", config, None, None,
                      serving=results, p50_ms=main_rate["p50_ms"], p99_ms=main_rate["p99_ms"])
     line["steps"] = args.serve_requests
     line["ms_per_step"] = round(1e3 / main_rate["rate_req_s"], 4) if main_rate["rate_req_s"] else None
     return line
+
+
+def serve_summary(args):
+    """The serving form attached to the headline line: p50 / p99 latency at
+    0.5 and 0.8 of the saturated request rate (fewer requests than --form serve)."""
+    import torch
+    eprint("serving leg ...")
+    results, config = serve_run(args, args.serve_requests_default)
+    torch.cuda.empty_cache()
+    return {"workload": config["workload"], "resident_GiB": config["resident_GiB"],
+            "requests_per_run": config["requests_per_run"], "results": results,
+            "p50_ms_at_0.8R": results["rate_0.8"]["p50_ms"], "p99_ms_at_0.8R": results["rate_0.8"]["p99_ms"]}
 
 
 # ------------------------------------------------------------ copy form ---
@@ -912,7 +1034,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--form", choices=("plain", "precision", "batch", "serve", "hessian", "copy"),
-                    default="plain")
+                    default="precision")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=100000)
@@ -925,6 +1047,14 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget", type=int, default=8192, help="server arena in MiB")
+    ap.add_argument("--serve-requests-default", type=int, default=1000,
+                    help="requests per rate point of the serving leg attached to the precision form")
+    ap.add_argument("--no-serve", dest="serve_in_default", action="store_false",
+                    help="precision form: skip the attached serving leg")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="host processes of the CPU oracle baseline (capped at the CPU count)")
+    ap.add_argument("--cpu-per-worker", type=int, default=25000,
+                    help="particles each oracle process evaluates in the CPU baseline")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

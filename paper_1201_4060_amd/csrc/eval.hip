@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
 // LDS-tiled variant: one workgroup of B threads walks `tiles_per_group`
 // consecutive Morton tiles (T^3 cells each), skipping empty ones.
 template <int N, typename CT, int C, bool GRAD, int T, int B>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(2))) void k_gather_tiled(GatherArgs a) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(sizeof(CT) == 8 ? 1 : 2))) void k_gather_tiled(GatherArgs a) {
     __shared__ u32x4 tile_v[tile_lds_bytes<N, CT, C, T, B>() / 16];
     const uint32_t nbt = a.nbuckets_finite + 1;
     const uint32_t b0 = uint32_t(logical_block(a.xcd_remap)) * a.tiles_per_group;
