@@ -155,6 +155,24 @@ bsi_status bsi_eval_ex(bsi_field* field, const double* pos_dev, int64_t P,
                        void* u_dev, void* grad_dev, const bsi_eval_config* cfg,
                        void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as bsi_eval_ex, bitwise, with the same arguments, but the
+ * binning workspace is a fixed device array of 128 MiB per GPU, part of the
+ * library's code object (each GPU the library runs on holds it until the
+ * process ends; its address is looked up once per device by bsi_ctx_create).
+ * The call allocates nothing and creates no events (the context's stage
+ * timing does not record it).  BSI_E_INVAL, with the bytes needed in
+ * bsi_last_error(), when the call's workspace (about 70 bytes per particle
+ * plus 8 per Morton tile of the field, for binned configurations) exceeds the
+ * array; use fewer particles per call or bsi_eval_ex then.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams or
+ * host threads) race and must not be issued; consecutive calls on one stream
+ * are ordered and safe.  Nothing in the array needs clearing between calls. */
+bsi_status bsi_eval_static(bsi_field* field, const double* pos_dev, int64_t P,
+                           void* u_dev, void* grad_dev, const bsi_eval_config* cfg,
+                           void* hip_stream);
+
 /* u, grad u and the second derivatives at P particles (Section 2: the l-th
  * derivative of the interpolant uses M^(l) = M D^l, here l = 2; Section 3 for
  * the tensor product).  u_dev [P][ncomp], grad_dev [P][ncomp][3] (NULL = not

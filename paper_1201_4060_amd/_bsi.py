@@ -89,6 +89,7 @@ SIGNATURES = {
     "bsi_field_get_coefficients": (ST, [VP, VP, VP]),
     "bsi_eval": (ST, [VP, VP, I64, VP, VP, VP]),
     "bsi_eval_ex": (ST, [VP, VP, I64, VP, VP, ctypes.POINTER(EvalConfig), VP]),
+    "bsi_eval_static": (ST, [VP, VP, I64, VP, VP, ctypes.POINTER(EvalConfig), VP]),
     "bsi_debug_cells": (ST, [VP, VP, I64, VP, VP, VP]),
     "bsi_eval_hessian": (ST, [VP, VP, I64, VP, VP, VP, VP]),
     "bsi_debug_bins": (ST, [VP, VP, I64, I32, VP, VP, VP, VP, ctypes.POINTER(I64), VP]),
@@ -217,6 +218,11 @@ def bsi_eval(field, pos, P, u, grad=None, stream=None):
 def bsi_eval_ex(field, pos, P, u, grad=None, cfg=None, stream=None):
     c = ctypes.byref(cfg) if cfg is not None else None
     _check(lib().bsi_eval_ex(field, _ptr(pos), P, _ptr(u), _ptr(grad), c, stream), "bsi_eval_ex")
+
+
+def bsi_eval_static(field, pos, P, u, grad=None, cfg=None, stream=None):
+    c = ctypes.byref(cfg) if cfg is not None else None
+    _check(lib().bsi_eval_static(field, _ptr(pos), P, _ptr(u), _ptr(grad), c, stream), "bsi_eval_static")
 
 
 def bsi_eval_hessian(field, pos, P, u, grad, hess, stream=None):

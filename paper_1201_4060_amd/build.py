@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libbsi.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "symbol.cpp", "fft.hip", "eval.hip", "hessian.hip", "batch.hip", "tune.hip", "synth.hip",
-           "server.cpp"]
+           "server.cpp", "static_eval.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

@@ -16,8 +16,16 @@ thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 
+namespace {
+thread_local int g_untimed = 0;
+}
+
+bool untimed() { return g_untimed > 0; }
+UntimedScope::UntimedScope() { ++g_untimed; }
+UntimedScope::~UntimedScope() { --g_untimed; }
+
 StageTimer::StageTimer(bsi_ctx* ctx, const char* stage, hipStream_t s) : ctx_(ctx), stage_(stage), s_(s) {
-    if (!ctx_ || !ctx_->timing) return;
+    if (!ctx_ || !ctx_->timing || untimed()) return;
     // no timing inside a stream capture (the events would belong to the graph)
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s_, &cs) != hipSuccess) {
@@ -213,6 +221,11 @@ bsi_status bsi_ctx_create(int device, void* hip_stream, bsi_ctx** out) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
     ctx->num_cus = prop.multiProcessorCount;
     ctx->lds_per_block = prop.sharedMemPerBlock;
+    const bsi_status st = static_scratch_init(device);
+    if (st != BSI_OK) {
+        delete ctx;
+        return st;
+    }
     *out = ctx;
     return BSI_OK;
 }

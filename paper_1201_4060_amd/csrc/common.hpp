@@ -175,6 +175,16 @@ struct bsi_field {
 
 namespace bsi {
 
+// While an UntimedScope lives on a host thread, StageTimer records nothing
+// (used by the entry point that must not create events or allocate).
+bool untimed();
+struct UntimedScope {
+    UntimedScope();
+    ~UntimedScope();
+    UntimedScope(const UntimedScope&) = delete;
+    UntimedScope& operator=(const UntimedScope&) = delete;
+};
+
 // Brackets the kernel launches of one stage with events when timing is on.
 class StageTimer {
    public:
@@ -225,6 +235,8 @@ bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, void* scra
 // u, grad u and the six second derivatives per component (hessian.hip)
 bsi_status hessian_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad, void* hess,
                        hipStream_t s);
+// device address of the static evaluation scratch (static_eval.hip), once per device
+bsi_status static_scratch_init(int device);
 bsi_status debug_bins_run(bsi_field* f, const double* pos, int64_t P, int tile, uint32_t* hist, uint32_t* offs,
                           uint32_t* perm, double* pos_sorted, hipStream_t s);
 
