@@ -1,4 +1,4 @@
-"""FP64 CPU oracle for B-spline interpolation of spectral fields.
+"""FP64 CPU oracle for B-spline (and comparison-method) interpolation of spectral fields.
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  The HIP library
@@ -21,7 +21,15 @@ methods for spectral codes" (SIAM J. Sci. Comput. 2012) defines:
                   the direct triple sum of weights times coefficients
                   (Section 3, n-mode products), with first derivatives,
                   and with second derivatives (M^(2) = M D^2, Section 2);
-* ``theory``   -- per-mode relative L2 errors (Section 5) used as pins.
+* ``methods``  -- the comparison methods' matrices: Lagrange through the N
+                  nearest points (linear for N = 2) and Hermite (Sections 2, 8);
+                  ``evaluate(..., basis="lagrange")`` runs them on grid values
+                  (prefilter variant NONE, c = 1);
+* ``hermite``  -- cubic Hermite in 3D: the 8 derivative fields per component
+                  from the spectrum and the plain 4^3-entry tensor sum
+                  (Sections 2, 3, 6);
+* ``theory``   -- per-mode relative L2 errors (Sections 5, 6, 8) of every
+                  method: the curves of Figs 3 and 4, used as pins.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against values fixed by
 the paper and by mathematics (printed matrices, closed forms, brute force on
@@ -29,15 +37,17 @@ tiny grids, polynomial reproduction, convergence order).
 """
 from .bspline import (bspline_matrix, derivative_matrix, matrix_f64,
                       derivative_matrix_f64)
-from .symbol import sinc_power_sum, prefilter_constants, INTERP, L2OPT
+from .symbol import sinc_power_sum, prefilter_constants, INTERP, L2OPT, NONE
 from .prefilter import prefilter
 from .evaluate import (cells, weights, weights2, evaluate, evaluate_hessian, inv_spacing, TWO_PI,
                        HESS_PAIRS)
-from . import theory
+from .methods import lagrange_matrix, hermite_matrix
+from . import theory, hermite
 
 __all__ = [
     "bspline_matrix", "derivative_matrix", "matrix_f64", "derivative_matrix_f64",
-    "sinc_power_sum", "prefilter_constants", "INTERP", "L2OPT",
+    "sinc_power_sum", "prefilter_constants", "INTERP", "L2OPT", "NONE",
+    "lagrange_matrix", "hermite_matrix", "hermite",
     "prefilter", "cells", "weights", "evaluate", "inv_spacing", "TWO_PI",
     "theory",
 ]

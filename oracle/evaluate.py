@@ -29,7 +29,26 @@ A vector field is handled per component (Section 3, last paragraph).
 """
 import numpy as np
 
-from .bspline import matrix_f64, derivative_matrix_f64
+from .bspline import bspline_matrix, derivative_matrix
+from .methods import lagrange_matrix, to_f64
+
+BASES = ("bspline", "lagrange")
+
+
+def basis_matrices(N, basis="bspline", l=1):
+    """M and M^(l) = M D^l (Section 2) of the basis, rounded to float64 once.
+
+    bspline  : M_(N) of Section 7 (the coefficient grid from the prefilter)
+    lagrange : Lagrange interpolation through the N nearest points (Section 8;
+               N = 2 is linear interpolation), on the grid values themselves
+    """
+    if basis == "bspline":
+        M = bspline_matrix(N)
+    elif basis == "lagrange":
+        M = lagrange_matrix(N)
+    else:
+        raise ValueError(f"unknown basis {basis!r}")
+    return to_f64(M), to_f64(derivative_matrix(M, l))
 
 TWO_PI = 2.0 * 3.141592653589793
 
@@ -64,20 +83,19 @@ def cells(pos, shape, lengths=(TWO_PI, TWO_PI, TWO_PI)):
     return cell, t, finite
 
 
-def weights(t, N, inv_h=1.0):
+def weights(t, N, inv_h=1.0, basis="bspline"):
     """w[P][N] and w'[P][N] for offsets t[P] (Section 2 matrices, Section 5 form)."""
-    M = matrix_f64(N)
-    M1 = derivative_matrix_f64(N, 1)
+    M, M1 = basis_matrices(N, basis, 1)
     powers = np.stack([t ** i for i in range(N)], axis=-1)     # [P][N]
     w = powers @ M.T
     wd = (powers @ M1.T) * inv_h
     return w, wd
 
 
-def weights2(t, N, inv_h=1.0):
+def weights2(t, N, inv_h=1.0, basis="bspline"):
     """Second-derivative weights w''[P][N]: Section 2 with l = 2, M^(2) = M D^2,
     times the chain factor (n/L)^2."""
-    M2 = derivative_matrix_f64(N, 2)
+    _, M2 = basis_matrices(N, basis, 2)
     powers = np.stack([t ** i for i in range(N)], axis=-1)
     return (powers @ M2.T) * (inv_h * inv_h)
 
@@ -88,10 +106,11 @@ def stencil_indices(cell_d, N, n):
     return np.mod(cell_d[:, None] - N // 2 + 1 + j[None, :], n)
 
 
-def evaluate(grid, pos, N, lengths=(TWO_PI, TWO_PI, TWO_PI), derivatives=True):
+def evaluate(grid, pos, N, lengths=(TWO_PI, TWO_PI, TWO_PI), derivatives=True, basis="bspline"):
     """Interpolate u and grad u at positions.
 
-    grid : float64 [C][n0][n1][n2] B-spline coefficients (output of prefilter)
+    grid : float64 [C][n0][n1][n2] B-spline coefficients (output of prefilter),
+           or grid values for basis="lagrange" (prefilter with variant NONE)
     pos  : float64 [P][3]
     Returns u [P][C] and (if derivatives) grad [P][C][3] with
     grad[p][c][d] = d u_c / d x_d.  Particles with a non-finite coordinate get NaN.
@@ -106,7 +125,7 @@ def evaluate(grid, pos, N, lengths=(TWO_PI, TWO_PI, TWO_PI), derivatives=True):
     cell, t, finite = cells(pos, shape, lengths)
     W, Wd, idx = [], [], []
     for d in range(3):
-        w, wd = weights(t[:, d], N, inv_spacing(shape[d], lengths[d]))
+        w, wd = weights(t[:, d], N, inv_spacing(shape[d], lengths[d]), basis)
         W.append(w)
         Wd.append(wd)
         idx.append(stencil_indices(cell[:, d], N, shape[d]))

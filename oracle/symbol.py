@@ -22,6 +22,7 @@ import numpy as np
 
 INTERP = "interp"
 L2OPT = "l2opt"
+NONE = "none"     # c = 1: the grid holds the field's values (Lagrange, linear, Hermite data)
 
 DEFAULT_TERMS = 20000
 
@@ -57,6 +58,8 @@ def _constants(n, N, variant, terms):
     # a pure function of its arguments, kept so that repeated prefilters of
     # the same grid size do not re-sum the lattice series
     kappa = signed_kappa(n)
+    if variant == NONE:
+        return np.ones(n)
     if variant == INTERP:
         return 1.0 / sinc_power_sum(kappa, N, terms)
     if variant == L2OPT:
