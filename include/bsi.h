@@ -66,16 +66,30 @@ typedef enum bsi_dtype { BSI_F64 = 0, BSI_F32 = 1, BSI_BF16 = 2 } bsi_dtype;
 
 /* Choice of c(k), Section 7.  L2OPT: c = F[B](kappa) / sum_i F[B](kappa+i)^2,
  * the L2-optimal constants the paper proposes.  INTERP: c = 1 / F_D[B_D](k),
- * the straightforward inverse of the sampled spline (exact at grid nodes). */
-typedef enum bsi_prefilter { BSI_PREFILTER_L2OPT = 0, BSI_PREFILTER_INTERP = 1 } bsi_prefilter;
+ * the straightforward inverse of the sampled spline (exact at grid nodes).
+ * NONE: c = 1, the grid holds the field's own values (the data of the
+ * Lagrange, linear and Hermite comparison methods, Section 8). */
+typedef enum bsi_prefilter {
+    BSI_PREFILTER_L2OPT = 0, BSI_PREFILTER_INTERP = 1, BSI_PREFILTER_NONE = 2
+} bsi_prefilter;
+
+/* Interpolation method (Section 2: u~ = f[u]^T M xbar on a cell; Section 8
+ * compares these).  BSPLINE: M_(N) of Section 7 on the prefiltered coefficient
+ * grid, orders 2 (linear), 4, 6.  LAGRANGE: the polynomial of degree N-1
+ * through the N nearest grid values (Section 5 stencil), orders 2 (linear), 4,
+ * 6; prefilter must be NONE.  HERMITE: cubic Hermite (order 4, Section 2 matrix)
+ * on the value and the derivatives of the field at the 2^3 corners of the cell
+ * (Section 3 tensor B; the 8 derivative fields per component come from 8
+ * inverse FFTs, Table 2); prefilter must be NONE. */
+typedef enum bsi_basis { BSI_BASIS_BSPLINE = 0, BSI_BASIS_LAGRANGE = 1, BSI_BASIS_HERMITE = 2 } bsi_basis;
 
 typedef struct bsi_field_desc {
-    int32_t n[3];        /* grid points per axis, each 2^a 3^b, 2*order <= n <= 1024   */
+    int32_t n[3];        /* grid points per axis, each 2^a 3^b, max(2*order, 8) <= n <= 1024 */
     int32_t ncomp;       /* 1 (scalar) or 3 (vector field, Section 3 last paragraph)   */
-    int32_t order;       /* spline order N (degree N-1): 4 or 6                        */
+    int32_t order;       /* N (degree N-1): 2, 4 or 6; 4 for BSI_BASIS_HERMITE          */
     int32_t coef;        /* bsi_dtype of the coefficient grid                          */
     int32_t prefilter;   /* bsi_prefilter                                              */
-    int32_t reserved;    /* must be 0                                                  */
+    int32_t basis;       /* bsi_basis (0 = B-spline, the paper's method)               */
     double length[3];    /* box lengths L_d; 0 means 2*pi                              */
 } bsi_field_desc;
 
@@ -115,10 +129,15 @@ const char* bsi_version(void);
 /* ---- fields ------------------------------------------------------------- */
 
 /* Validate `desc` and allocate the field's coefficient grid on the device.
- * BSI_E_INVAL for bad sizes/ncomp/dtype/lengths, BSI_E_UNSUPPORTED for an
- * order other than 4 or 6 or an n that is not 2^a 3^b, BSI_E_NOMEM if the
- * grid does not fit.  The grid is (n0+N-1)(n1+N-1)(n2+N-1)*ncomp elements:
- * the periodic grid plus N-1 ghost planes per axis, components interleaved. */
+ * BSI_E_INVAL for bad sizes/ncomp/dtype/lengths/basis or a basis whose
+ * prefilter must be NONE, BSI_E_UNSUPPORTED for another order or an n that is
+ * not 2^a 3^b, BSI_E_NOMEM if the grid does not fit.  The grid is
+ * (n0+N-1)(n1+N-1)(n2+N-1)*ncomp elements: the periodic grid plus N-1 ghost
+ * planes per axis, components interleaved.  A Hermite field stores its 8
+ * derivative fields interleaved on a doubled grid: entry 2g+a of each axis
+ * holds the a-th (0 or 1) derivative along that axis, in grid units (spacing
+ * one), at grid point g; (2n0+2)(2n1+2)(2n2+2)*ncomp elements with 2 ghost
+ * entries per axis, 8 times the memory of one grid (Table 2's (N/2)^3 fields). */
 bsi_status bsi_field_create(bsi_ctx* ctx, const bsi_field_desc* desc, bsi_field** out);
 void bsi_field_destroy(bsi_field* field);
 /* Device bytes held by the field (grid and counters). */
@@ -128,23 +147,31 @@ size_t bsi_field_bytes(const bsi_field* field);
  * complex128 if uhat_prec == BSI_F64 or complex64 if BSI_F32.  The symbol
  * product is formed and applied in FP64, then one inverse 3D real FFT runs in
  * FP64 (BSI_F64 grid) or FP32 (BSI_F32 / BSI_BF16 grid; BF16 is a
- * round-to-nearest-even cast of the FP32 result).  uhat is only read. */
+ * round-to-nearest-even cast of the FP32 result).  uhat is only read.  With
+ * prefilter NONE the grid is the field's values; for a Hermite field the call
+ * runs 8 inverse FFTs, one per derivative field, the spectrum multiplied by
+ * prod_d (i 2 pi k'_d / n_d)^(a_d) in FP64 (zero at the Nyquist index of a
+ * differentiated axis). */
 bsi_status bsi_field_set_spectrum(bsi_field* field, const void* uhat_dev,
                                   int32_t uhat_prec, void* hip_stream);
 
 /* Load the coefficient grid directly: grid_dev is FP64 [ncomp][n0][n1][n2]
- * (component-major, no ghosts), cast to the field's storage type.  Lets the
- * evaluation be checked on a grid computed elsewhere. */
+ * (component-major, no ghosts; [ncomp][2n0][2n1][2n2] in the interleaved
+ * layout above for a Hermite field), cast to the field's storage type.  Lets
+ * the evaluation be checked on a grid computed elsewhere. */
 bsi_status bsi_field_set_coefficients(bsi_field* field, const double* grid_dev,
                                       void* hip_stream);
 /* Read the coefficient grid back as FP64 [ncomp][n0][n1][n2] (widened from
- * the storage type). */
+ * the storage type; the interleaved [ncomp][2n0][2n1][2n2] for Hermite). */
 bsi_status bsi_field_get_coefficients(const bsi_field* field, double* grid_dev,
                                       void* hip_stream);
 
 /* ---- evaluation (Sections 2, 3, 5; Table 1) ----------------------------- */
 
-/* Interpolate u (and grad u if grad_dev != NULL) at P particle positions.
+/* Interpolate u (and grad u if grad_dev != NULL) at P particle positions
+ * with the field's method (B-spline, Lagrange, linear or Hermite: same stencil
+ * rule and contraction, Sections 2, 3, 5; Hermite fields are evaluated one
+ * lane per binned particle, never from LDS tiles).
  * pos_dev: FP64 [P][3]; u_dev: [P][ncomp]; grad_dev: [P][ncomp][3]; device
  * pointers, 8-byte aligned.  0 <= P < 2^31; P == 0 does nothing. */
 bsi_status bsi_eval(bsi_field* field, const double* pos_dev, int64_t P,
@@ -173,7 +200,8 @@ bsi_status bsi_eval_static(bsi_field* field, const double* pos_dev, int64_t P,
                            void* u_dev, void* grad_dev, const bsi_eval_config* cfg,
                            void* hip_stream);
 
-/* u, grad u and the second derivatives at P particles (Section 2: the l-th
+/* (B-spline fields of orders 4 and 6; BSI_E_UNSUPPORTED for other fields.)
+ * u, grad u and the second derivatives at P particles (Section 2: the l-th
  * derivative of the interpolant uses M^(l) = M D^l, here l = 2; Section 3 for
  * the tensor product).  u_dev [P][ncomp], grad_dev [P][ncomp][3] (NULL = not
  * computed), hess_dev [P][ncomp][6] with hess[p][c][m] = d2 u_c / dx_i dx_j for
@@ -225,7 +253,8 @@ typedef struct bsi_eval_item {
 
 typedef struct bsi_batch bsi_batch;
 
-/* Plan the evaluation of `count` items (1..65535) as one unit of work: every
+/* (Items must be B-spline fields of orders 4 and 6; BSI_E_UNSUPPORTED otherwise.)
+ * Plan the evaluation of `count` items (1..65535) as one unit of work: every
  * item's particles are binned by the Morton tile of its own sort granularity,
  * and one persistent gather kernel walks a shared work list -- the non-empty
  * tiles of the items gathered from LDS tiles (8^3 cells) and groups of

@@ -11,8 +11,10 @@ torch is used for device memory and streams only.
 """
 from . import _bsi
 from ._bsi import (BsiError, BSI_F64, BSI_F32, BSI_BF16, BSI_PREFILTER_L2OPT,
-                   BSI_PREFILTER_INTERP, EvalConfig)
+                   BSI_PREFILTER_INTERP, BSI_PREFILTER_NONE, BSI_BASIS_BSPLINE, BSI_BASIS_LAGRANGE,
+                   BSI_BASIS_HERMITE, EvalConfig)
 from .api import Batch, Context, Field, Server
 
 __all__ = ["_bsi", "BsiError", "BSI_F64", "BSI_F32", "BSI_BF16", "BSI_PREFILTER_L2OPT",
-           "BSI_PREFILTER_INTERP", "EvalConfig", "Batch", "Context", "Field", "Server"]
+           "BSI_PREFILTER_INTERP", "BSI_PREFILTER_NONE", "BSI_BASIS_BSPLINE", "BSI_BASIS_LAGRANGE",
+           "BSI_BASIS_HERMITE", "EvalConfig", "Batch", "Context", "Field", "Server"]

@@ -12,7 +12,8 @@ BSI_OK = 0
 STATUS_NAMES = {0: "BSI_OK", 1: "BSI_E_INVAL", 2: "BSI_E_NOMEM", 3: "BSI_E_UNSUPPORTED",
                 4: "BSI_E_DEVICE", 5: "BSI_E_BUSY", 6: "BSI_E_CANCELLED"}
 BSI_F64, BSI_F32, BSI_BF16 = 0, 1, 2
-BSI_PREFILTER_L2OPT, BSI_PREFILTER_INTERP = 0, 1
+BSI_PREFILTER_L2OPT, BSI_PREFILTER_INTERP, BSI_PREFILTER_NONE = 0, 1, 2
+BSI_BASIS_BSPLINE, BSI_BASIS_LAGRANGE, BSI_BASIS_HERMITE = 0, 1, 2
 
 
 class BsiError(RuntimeError):
@@ -23,7 +24,7 @@ class BsiError(RuntimeError):
 
 class FieldDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("ncomp", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("coef", ctypes.c_int32), ("prefilter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("coef", ctypes.c_int32), ("prefilter", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("length", ctypes.c_double * 3)]
 
 
@@ -175,12 +176,13 @@ def bsi_version():
     return lib().bsi_version().decode()
 
 
-def make_desc(n, ncomp, order, coef=BSI_F32, prefilter=BSI_PREFILTER_L2OPT, length=(0.0, 0.0, 0.0)):
+def make_desc(n, ncomp, order, coef=BSI_F32, prefilter=BSI_PREFILTER_L2OPT, length=(0.0, 0.0, 0.0),
+              basis=BSI_BASIS_BSPLINE):
     if isinstance(n, int):
         n = (n, n, n)
     d = FieldDesc()
     d.n = (ctypes.c_int32 * 3)(*n)
-    d.ncomp, d.order, d.coef, d.prefilter, d.reserved = ncomp, order, coef, prefilter, 0
+    d.ncomp, d.order, d.coef, d.prefilter, d.basis = ncomp, order, coef, prefilter, basis
     d.length = (ctypes.c_double * 3)(*length)
     return d
 

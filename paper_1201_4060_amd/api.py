@@ -36,11 +36,11 @@ class Field:
     """bsi_field: a coefficient grid of a scalar or 3-component periodic field."""
 
     def __init__(self, ctx, n, ncomp, order, coef=_bsi.BSI_F32, prefilter=_bsi.BSI_PREFILTER_L2OPT,
-                 length=(0.0, 0.0, 0.0)):
+                 length=(0.0, 0.0, 0.0), basis=_bsi.BSI_BASIS_BSPLINE):
         self.ctx = ctx
         self.n = (n, n, n) if isinstance(n, int) else tuple(n)
-        self.ncomp, self.order, self.coef = ncomp, order, coef
-        self.desc = _bsi.make_desc(self.n, ncomp, order, coef, prefilter, length)
+        self.ncomp, self.order, self.coef, self.basis = ncomp, order, coef, basis
+        self.desc = _bsi.make_desc(self.n, ncomp, order, coef, prefilter, length, basis)
         self.handle = _bsi.bsi_field_create(ctx.handle, self.desc)
 
     @property
@@ -69,14 +69,21 @@ class Field:
         prec = {torch.complex128: _bsi.BSI_F64, torch.complex64: _bsi.BSI_F32}[uhat.dtype]
         _bsi.bsi_field_set_spectrum(self.handle, uhat, prec, _stream())
 
+    @property
+    def grid_shape(self):
+        """Shape of the dense coefficient grid: [ncomp][n0][n1][n2], or for a
+        Hermite field the interleaved [ncomp][2 n0][2 n1][2 n2]."""
+        s = 2 if self.basis == _bsi.BSI_BASIS_HERMITE else 1
+        return (self.ncomp,) + tuple(s * v for v in self.n)
+
     def set_coefficients(self, grid):
-        """grid: float64 device tensor [ncomp][n0][n1][n2]."""
+        """grid: float64 device tensor of shape grid_shape."""
         assert grid.is_cuda and grid.is_contiguous() and grid.dtype == torch.float64
-        assert tuple(grid.shape) == (self.ncomp,) + self.n
+        assert tuple(grid.shape) == self.grid_shape
         _bsi.bsi_field_set_coefficients(self.handle, grid, _stream())
 
     def get_coefficients(self):
-        out = torch.empty((self.ncomp,) + self.n, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        out = torch.empty(self.grid_shape, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
         _bsi.bsi_field_get_coefficients(self.handle, out, _stream())
         return out
 

@@ -279,18 +279,26 @@ bsi_status bsi_field_create(bsi_ctx* ctx, const bsi_field_desc* desc, bsi_field*
     clear_error();
     BSI_CHECK(ctx && desc && out, BSI_E_INVAL, "NULL argument");
     *out = nullptr;
-    BSI_CHECK(desc->order == 4 || desc->order == 6, BSI_E_UNSUPPORTED,
-              "only spline orders 4 and 6 are implemented");
+    BSI_CHECK(desc->basis == BSI_BASIS_BSPLINE || desc->basis == BSI_BASIS_LAGRANGE ||
+                  desc->basis == BSI_BASIS_HERMITE,
+              BSI_E_INVAL, "unknown basis");
+    if (desc->basis == BSI_BASIS_HERMITE)
+        BSI_CHECK(desc->order == 4, BSI_E_UNSUPPORTED, "Hermite interpolation is implemented for order 4");
+    else
+        BSI_CHECK(desc->order == 2 || desc->order == 4 || desc->order == 6, BSI_E_UNSUPPORTED,
+                  "only orders 2, 4 and 6 are implemented");
     BSI_CHECK(desc->ncomp == 1 || desc->ncomp == 3, BSI_E_INVAL, "ncomp must be 1 or 3");
     BSI_CHECK(desc->coef == BSI_F64 || desc->coef == BSI_F32 || desc->coef == BSI_BF16, BSI_E_INVAL,
               "unknown coefficient dtype");
-    BSI_CHECK(desc->prefilter == BSI_PREFILTER_L2OPT || desc->prefilter == BSI_PREFILTER_INTERP,
+    BSI_CHECK(desc->prefilter == BSI_PREFILTER_L2OPT || desc->prefilter == BSI_PREFILTER_INTERP ||
+                  desc->prefilter == BSI_PREFILTER_NONE,
               BSI_E_INVAL, "unknown prefilter variant");
-    BSI_CHECK(desc->reserved == 0, BSI_E_INVAL, "reserved field must be 0");
+    BSI_CHECK(desc->basis == BSI_BASIS_BSPLINE || desc->prefilter == BSI_PREFILTER_NONE, BSI_E_INVAL,
+              "Lagrange and Hermite fields hold the field's values: prefilter must be NONE");
     for (int d = 0; d < 3; ++d) {
         const int n = desc->n[d];
-        BSI_CHECK(n >= 2 * desc->order && n <= 1024 && n % 2 == 0, BSI_E_INVAL,
-                  "each n must be even with 2*order <= n <= 1024");
+        BSI_CHECK(n >= 2 * desc->order && n >= 8 && n <= 1024 && n % 2 == 0, BSI_E_INVAL,
+                  "each n must be even with max(2*order, 8) <= n <= 1024");
         BSI_CHECK(is_2a3b(n) && n >= 8, BSI_E_UNSUPPORTED, "each n must be of the form 2^a 3^b");
         const double L = desc->length[d];
         BSI_CHECK(L == 0.0 || (std::isfinite(L) && L > 0.0), BSI_E_INVAL, "lengths must be > 0");
@@ -302,10 +310,16 @@ bsi_status bsi_field_create(bsi_ctx* ctx, const bsi_field_desc* desc, bsi_field*
     f->desc = *desc;
     f->N = desc->order;
     f->C = desc->ncomp;
-    f->padlo = f->N / 2 - 1;
+    f->basis = desc->basis;
+    const bool herm = desc->basis == BSI_BASIS_HERMITE;
+    f->cs = herm ? 2 : 1;
+    // B-spline / Lagrange: the stencil of cell c is padded indices [c, c + N);
+    // Hermite: doubled indices [2c, 2c + 4) (value and derivative at c, c + 1)
+    f->padlo = herm ? 0 : f->N / 2 - 1;
     for (int d = 0; d < 3; ++d) {
         f->n[d] = desc->n[d];
-        f->P[d] = desc->n[d] + f->N - 1;
+        f->gn[d] = f->cs * desc->n[d];
+        f->P[d] = herm ? 2 * desc->n[d] + 2 : desc->n[d] + f->N - 1;
         f->L[d] = desc->length[d] == 0.0 ? 2.0 * 3.141592653589793 : desc->length[d];
         f->inv_h[d] = double(f->n[d]) / f->L[d];
     }

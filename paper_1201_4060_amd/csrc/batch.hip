@@ -345,6 +345,8 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
         const std::string tag = "item " + std::to_string(i) + ": ";
         BSI_CHECK(it.field != nullptr, BSI_E_INVAL, tag + "field is NULL");
         BSI_CHECK(it.field->ctx == ctx, BSI_E_INVAL, tag + "field belongs to another context");
+        BSI_CHECK(it.field->basis == BSI_BASIS_BSPLINE && (it.field->N == 4 || it.field->N == 6),
+                  BSI_E_UNSUPPORTED, tag + "batches hold B-spline fields of orders 4 and 6");
         BSI_CHECK(it.field->desc.coef == coef, BSI_E_INVAL,
                   tag + "a batch holds fields of one coefficient type");
         BSI_CHECK(it.P >= 0 && it.P < (int64_t(1) << 31), BSI_E_INVAL, tag + "P must be in [0, 2^31)");
@@ -407,6 +409,8 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
         g.ih2 = f->inv_h[2];
         g.xcd_remap = 0;
         g.tiles_per_group = 1;
+        g.basis = BSI_BASIS_BSPLINE;
+        g.cs = 1;
         const size_t nbf = bin_bucket_count(f, tile);
         g.nbuckets_finite = uint32_t(nbf);
         x.N = f->N;

@@ -112,6 +112,48 @@ struct BSpline {
     }
 };
 
+// Lagrange interpolation through the N nearest grid values (Section 8), whose
+// nodes in a cell's local coordinate are j - N/2 + 1 for stencil point j
+// (Section 5 rule): row j = monomial coefficients of the j-th Lagrange basis
+// polynomial, built at compile time as an integer numerator polynomial over an
+// integer denominator (one rounding per coefficient).  M^(1) = M D.
+template <int N>
+struct LagrangeM {
+    double M[N][N];
+    double M1[N][N];
+    constexpr LagrangeM() : M{}, M1{} {
+        for (int j = 0; j < N; ++j) {
+            long long poly[N + 1] = {};
+            poly[0] = 1;
+            long long den = 1;
+            int deg = 0;
+            for (int k = 0; k < N; ++k) {
+                if (k == j) continue;
+                const long long node = k - N / 2 + 1;
+                for (int i = deg + 1; i > 0; --i) poly[i] = poly[i - 1] - node * poly[i];
+                poly[0] = -node * poly[0];
+                ++deg;
+                den *= (j - k);
+            }
+            for (int i = 0; i < N; ++i) {
+                M[j][i] = double(poly[i]) / double(den);
+                M1[j][i] = (i + 1 < N) ? double((i + 1) * poly[i + 1]) / double(den) : 0.0;
+            }
+        }
+    }
+};
+
+// Cubic Hermite interpolation (Section 2): the printed matrix for the data
+// f = (u(0), u'(0), u(1), u'(1)) of a cell; M^(1) = M D.
+struct HermiteM {
+    double M[4][4];
+    double M1[4][4];
+    constexpr HermiteM() : M{{1, 0, -3, 2}, {0, 1, -2, 1}, {0, 0, 3, -2}, {0, 0, -1, 1}}, M1{} {
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) M1[r][c] = (c + 1 < 4) ? (c + 1) * M[r][c + 1] : 0.0;
+    }
+};
+
 // B_M(s) at an integer s: the t = 0 column of M_(M) holds the integer samples
 // of the centred B-spline (row j <-> s = M/2 - 1 - j).
 inline double bspline_integer_sample(int M, int s) {
@@ -161,9 +203,12 @@ struct bsi_field {
     bsi_field_desc desc{};
     int N = 4;
     int C = 1;
+    int basis = BSI_BASIS_BSPLINE;
+    int cs = 1;            // stored grid points per cell along an axis: 1, or 2 (Hermite: value, derivative)
     int n[3] = {0, 0, 0};
-    int P[3] = {0, 0, 0};  // padded extents n + N - 1
-    int padlo = 1;         // ghost planes below index 0 (N/2 - 1)
+    int gn[3] = {0, 0, 0}; // periodic extent of the stored grid: cs * n
+    int P[3] = {0, 0, 0};  // padded extents gn + N - 1 (Hermite: 2n + 2)
+    int padlo = 1;         // ghost planes below index 0 (N/2 - 1; Hermite 0)
     int pitch2 = 0;        // elements between consecutive (p0, p1) rows: P2*C rounded up to 16 B
     double L[3] = {0, 0, 0};
     double inv_h[3] = {0, 0, 0};
@@ -205,7 +250,9 @@ bsi_status get_workspace(std::map<hipStream_t, Workspace>& m, hipStream_t s, siz
 bsi_status get_twiddles(bsi_ctx* ctx, int len, bool dbl, const void** out);
 bsi_status get_ctable(bsi_ctx* ctx, int n, int order, int variant, const double** out);
 
-// host-side prefilter constants (symbol.cpp)
+// host-side prefilter constants (symbol.cpp); variant DERIVATIVE_TABLE gives
+// the factor 2 pi k'/n of a derivative along the axis (0 at the Nyquist index)
+constexpr int DERIVATIVE_TABLE = 100;
 void prefilter_table(int n, int order, int variant, double* out);
 
 // launchers

@@ -109,7 +109,10 @@ void launch_gather_t(const GatherArgs& ga, bool grad, unsigned nb, unsigned bloc
 template <typename CT>
 void launch_gather_ct(int N, int C, const GatherArgs& ga, bool grad, unsigned nb, unsigned block,
                       hipStream_t s) {
-    if (N == 4) {
+    if (N == 2) {
+        if (C == 1) launch_gather_t<2, CT, 1>(ga, grad, nb, block, s);
+        else launch_gather_t<2, CT, 3>(ga, grad, nb, block, s);
+    } else if (N == 4) {
         if (C == 1) launch_gather_t<4, CT, 1>(ga, grad, nb, block, s);
         else launch_gather_t<4, CT, 3>(ga, grad, nb, block, s);
     } else {
@@ -170,6 +173,11 @@ bool launch_tiled_c(int T, const GatherArgs& ga, bool grad, bool wide, unsigned 
 template <typename CT>
 bool launch_tiled_ct(int N, int C, int T, const GatherArgs& ga, bool grad, bool wide, unsigned nb,
                      hipStream_t s) {
+    if (N == 2) {   // linear: 8^3-cell tiles only
+        if (T != 8) return false;
+        return C == 1 ? launch_tiled_T<2, CT, 1, 8>(ga, grad, wide, nb, s)
+                      : launch_tiled_T<2, CT, 3, 8>(ga, grad, wide, nb, s);
+    }
     if (N == 4)
         return C == 1 ? launch_tiled_c<4, CT, 1>(T, ga, grad, wide, nb, s)
                       : launch_tiled_c<4, CT, 3>(T, ga, grad, wide, nb, s);
@@ -191,6 +199,7 @@ bool tile_ok_rt(int T) {
 
 template <typename CT>
 bool tile_ok_ct(int N, int C, int T) {
+    if (N == 2) return T == 8 && (C == 1 ? tile_ok<2, CT, 1, 8>() : tile_ok<2, CT, 3, 8>());
     if (N == 4) return C == 1 ? tile_ok_rt<4, CT, 1>(T) : tile_ok_rt<4, CT, 3>(T);
     return C == 1 ? tile_ok_rt<6, CT, 1>(T) : tile_ok_rt<6, CT, 3>(T);
 }
@@ -257,6 +266,8 @@ bsi_status bin_run(bsi_field* f, const double* pos, long P, int tile, void* scra
 }
 
 bool tiled_supported(const bsi_field* f, int tile) {
+    // Hermite fields (two stored entries per cell and axis) use the direct gather
+    if (f->cs != 1) return false;
     if (f->desc.coef == BSI_F64) return tile_ok_ct<double>(f->N, f->C, tile);
     if (f->desc.coef == BSI_F32) return tile_ok_ct<float>(f->N, f->C, tile);
     return tile_ok_ct<uint16_t>(f->N, f->C, tile);
@@ -329,6 +340,8 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
     ga.ih2 = f->inv_h[2];
     ga.xcd_remap = (perm && cfg.xcd_remap) ? 1 : 0;
     ga.nbuckets_finite = uint32_t(nbf);
+    ga.basis = f->basis;
+    ga.cs = f->cs;
     const bool g = grad != nullptr;
     StageTimer tm(f->ctx, "gather", s);
     const bool tiled = perm && cfg.variant == 0 && tiled_supported(f, tile);

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
                                                   long sAxis, long sOther, long sComp, long oAxis, long oOther,
                                                   long oComp, const double* cAxis,
                                                   const double* cOther, const double* c2,
-                                                  const cplx<T>* twg) {
+                                                  const cplx<T>* twg, int quarter) {
     using Cfg = StridedCfg<T, LEN, strided_lds_kb<LEN, FIRST>()>;
     constexpr int W = Cfg::W;
     constexpr int LP = LEN + 1;
@@ -242,7 +242,11 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const double m = (ca[q] * cO) * cw;
-            v[q] = {T(re[q] * m), T(im[q] * m)};
+            const double a = re[q] * m, b = im[q] * m;
+            // times i^quarter (the i's of derivative factors; 0 otherwise)
+            const double x = quarter == 0 ? a : quarter == 1 ? -b : quarter == 2 ? -a : b;
+            const double y = quarter == 0 ? b : quarter == 1 ? a : quarter == 2 ? -b : -a;
+            v[q] = {T(x), T(y)};
         }
     } else {
         const cplx<T>* src = reinterpret_cast<const cplx<T>*>(in);
@@ -297,10 +301,13 @@ struct C2rCfg {
 // Pass C.  work[c][g0][g1][k2] (k2 <= M, rows of Hp) -> grid[p0][p1][p2][c] with ghost
 // planes: padded index p holds grid index (p - padlo) mod n on every axis.
 // tw[m] = exp(+2 pi i m / (2M)), m < 2M.
+// A Hermite field stores the transformed field at stride st = 2 with offset
+// (a0, a1, a2) on every axis (the derivative orders); otherwise st = 1, a = 0.
 template <typename T, typename OutT, int M, int C>
 __global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, int Hp, OutT* __restrict__ grid,
                                              int n0, int n1, int P0, int P1, int P2, int pitch2,
-                                             int padlo, const cplx<T>* __restrict__ twg) {
+                                             int padlo, const cplx<T>* __restrict__ twg, int st, int a0,
+                                             int a1, int a2) {
     using Cfg = C2rCfg<T, M, C>;
     constexpr int H = M + 1;
     constexpr int LP = M + 2;
@@ -364,19 +371,24 @@ __global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, i
         const long line = line0 + l;
         if (line >= nlines) break;
         const int g0 = int(line / n1), g1 = int(line % n1);
-        // padded rows holding grid row g: g + padlo, and one periodic ghost copy
-        // (g + padlo - n or g + padlo + n) when that falls inside [0, P)
-        const int p0a = g0 + padlo;
-        const int p0b = (p0a - n0 >= 0) ? p0a - n0 : ((p0a + n0 < P0) ? p0a + n0 : -1);
-        const int p1a = g1 + padlo;
-        const int p1b = (p1a - n1 >= 0) ? p1a - n1 : ((p1a + n1 < P1) ? p1a + n1 : -1);
+        // padded rows holding grid row g: st g + a + padlo, and one periodic
+        // ghost copy (minus or plus st n) when that falls inside [0, P)
+        const int p0a = st * g0 + a0 + padlo;
+        const int p0b = (p0a - st * n0 >= 0) ? p0a - st * n0 : ((p0a + st * n0 < P0) ? p0a + st * n0 : -1);
+        const int p1a = st * g1 + a1 + padlo;
+        const int p1b = (p1a - st * n1 >= 0) ? p1a - st * n1 : ((p1a + st * n1 < P1) ? p1a + st * n1 : -1);
         OutT* r_aa = grid + (long(p0a) * P1 + p1a) * pitch2;
         OutT* r_ab = p1b >= 0 ? grid + (long(p0a) * P1 + p1b) * pitch2 : nullptr;
         OutT* r_ba = p0b >= 0 ? grid + (long(p0b) * P1 + p1a) * pitch2 : nullptr;
         OutT* r_bb = (p0b >= 0 && p1b >= 0) ? grid + (long(p0b) * P1 + p1b) * pitch2 : nullptr;
         for (int e = tid; e < rowElems; e += Cfg::THREADS) {
             const int p2 = e / C, c = e % C;
-            int g2 = p2 - padlo;
+            int q2 = p2 - padlo - a2;
+            if (st == 2) {
+                if (q2 & 1) continue;   // another derivative field's entry
+                q2 >>= 1;
+            }
+            int g2 = q2;
             if (g2 < 0) g2 += 2 * M;
             else if (g2 >= 2 * M) g2 -= 2 * M;
             const cplx<T> z = zb[(l * C + c) * LP + (g2 >> 1)];
@@ -436,7 +448,7 @@ template <typename T, typename InT, bool FIRST>
 bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, long sAxis, long sOther,
                        long sComp, long oAxis, long oOther, long oComp, const double* cAxis,
                        const double* cOther, const double* c2,
-                       const cplx<T>* tw, hipStream_t s, int* Wout) {
+                       const cplx<T>* tw, hipStream_t s, int* Wout, int quarter = 0) {
 #define BSI_AXIS_CASE(L)                                                                           \
     case L: {                                                                                      \
         using Cfg = StridedCfg<T, L, strided_lds_kb<L, FIRST>()>;                                  \
@@ -445,7 +457,8 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
         const dim3 g = fft_remap<L, FIRST>() ? dim3(unsigned(gx) * grid.y * grid.z)              \
                                               : dim3(unsigned(gx), grid.y, grid.z);              \
         hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), g, dim3(Cfg::THREADS), 0, s, in, out, H, gx, \
-                           int(grid.y), sAxis, sOther, sComp, oAxis, oOther, oComp, cAxis, cOther, c2, tw); \
+                           int(grid.y), sAxis, sOther, sComp, oAxis, oOther, oComp, cAxis, cOther, c2, tw, \
+                           quarter);                                                              \
         break;                                                                                     \
     }
     switch (len) {
@@ -475,14 +488,15 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
 
 template <typename T, typename OutT, int C>
 bsi_status launch_c2r(int M, const cplx<T>* work, int Hp, OutT* grid, int n0, int n1, int P0, int P1, int P2,
-                      int pitch2, int padlo, const cplx<T>* tw, hipStream_t s) {
+                      int pitch2, int padlo, const cplx<T>* tw, hipStream_t s, int st = 1, int a0 = 0,
+                      int a1 = 0, int a2 = 0) {
     const long nlines = long(n0) * n1;
 #define BSI_C2R_CASE(MM)                                                                           \
     case MM: {                                                                                     \
         using Cfg = C2rCfg<T, MM, C>;                                                                 \
         const unsigned nb = unsigned((nlines + Cfg::LINES - 1) / Cfg::LINES);                      \
         hipLaunchKernelGGL((k_c2r<T, OutT, MM, C>), dim3(nb), dim3(Cfg::THREADS), 0, s, work, Hp, grid, \
-                           n0, n1, P0, P1, P2, pitch2, padlo, tw);                                 \
+                           n0, n1, P0, P1, P2, pitch2, padlo, tw, st, a0, a1, a2);                \
         break;                                                                                     \
     }
     switch (M) {
@@ -511,6 +525,11 @@ bsi_status launch_c2r(int M, const cplx<T>* work, int Hp, OutT* grid, int n0, in
 }
 
 template <typename T, typename InT, typename OutT>
+bsi_status prefilter_pass(bsi_field* f, const InT* uhat, OutT* grid, cplx<T>* work, int H, int Hp, long sComp,
+                          long wComp, const double* const* ct, const int* a, int st, int quarter,
+                          const void* tw0, const void* tw1, const void* tw2, hipStream_t s);
+
+template <typename T, typename InT, typename OutT>
 bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_t s) {
     bsi_ctx* ctx = f->ctx;
     const int n0 = f->n[0], n1 = f->n[1], n2 = f->n[2], C = f->C;
@@ -523,10 +542,6 @@ bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_
     void* wsp = nullptr;
     BSI_TRY(get_workspace(ctx->fft_ws, s, elems * sizeof(cplx<T>), &wsp));
     cplx<T>* work = static_cast<cplx<T>*>(wsp);
-    const double *c0, *c1, *c2;
-    BSI_TRY(get_ctable(ctx, n0, f->N, f->desc.prefilter, &c0));
-    BSI_TRY(get_ctable(ctx, n1, f->N, f->desc.prefilter, &c1));
-    BSI_TRY(get_ctable(ctx, n2, f->N, f->desc.prefilter, &c2));
     const void *tw0, *tw1, *tw2;
     const bool dbl = sizeof(T) == 8;
     BSI_TRY(get_twiddles(ctx, n0, dbl, &tw0));
@@ -534,13 +549,38 @@ bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_
     BSI_TRY(get_twiddles(ctx, n2, dbl, &tw2));
     const long sComp = long(n0) * n1 * H;    // caller's spectrum
     const long wComp = long(n0) * n1 * Hp;   // work buffer
+    // one inverse FFT per stored field: the prefiltered (or plain) field, or
+    // for Hermite the 8 derivative fields d^(a0+a1+a2) u / ds0^a0 ds1^a1 ds2^a2
+    const bool herm = f->basis == BSI_BASIS_HERMITE;
+    for (int fld = 0; fld < (herm ? 8 : 1); ++fld) {
+        const int a[3] = {(fld >> 2) & 1, (fld >> 1) & 1, fld & 1};
+        const double* ct[3];
+        const int nn[3] = {n0, n1, n2};
+        for (int d = 0; d < 3; ++d)
+            BSI_TRY(get_ctable(ctx, nn[d], f->N, herm ? (a[d] ? DERIVATIVE_TABLE : BSI_PREFILTER_NONE)
+                                                      : f->desc.prefilter, &ct[d]));
+        BSI_TRY((prefilter_pass<T, InT, OutT>(f, uhat, grid, work, H, Hp, sComp, wComp, ct, a, herm ? 2 : 1,
+                                              (a[0] + a[1] + a[2]) & 3, tw0, tw1, tw2, s)));
+    }
+    return BSI_OK;
+}
+
+// The three passes of one inverse FFT: symbol tables ct[d] per axis, the
+// product times i^quarter, written at stride st with offsets a[] (see k_c2r).
+template <typename T, typename InT, typename OutT>
+bsi_status prefilter_pass(bsi_field* f, const InT* uhat, OutT* grid, cplx<T>* work, int H, int Hp, long sComp,
+                          long wComp, const double* const* ct, const int* a, int st, int quarter,
+                          const void* tw0, const void* tw1, const void* tw2, hipStream_t s) {
+    bsi_ctx* ctx = f->ctx;
+    const int n0 = f->n[0], n1 = f->n[1], n2 = f->n[2], C = f->C;
+    const double *c0 = ct[0], *c1 = ct[1], *c2 = ct[2];
     int W = 0;
     // pass A: axis 0 (stride n1*H in, n1*Hp out), other = k1 (stride H in, Hp out)
     {
     StageTimer tm(ctx, "fft_axis0", s);
     BSI_TRY((launch_axis<T, InT, true>(n0, dim3(1, n1, C), uhat, work, H, long(n1) * H, long(H), sComp,
                                        long(n1) * Hp, long(Hp), wComp, c0, c1, c2,
-                                       static_cast<const cplx<T>*>(tw0), s, &W)));
+                                       static_cast<const cplx<T>*>(tw0), s, &W, quarter)));
     }
     // pass B: axis 1 (stride Hp), other = k0 (stride n1*Hp), in place
     {
@@ -554,9 +594,9 @@ bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_
     StageTimer tm(ctx, "fft_c2r", s);
     if (C == 1)
         return launch_c2r<T, OutT, 1>(M, work, Hp, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, f->padlo,
-                                      static_cast<const cplx<T>*>(tw2), s);
+                                      static_cast<const cplx<T>*>(tw2), s, st, a[0], a[1], a[2]);
     return launch_c2r<T, OutT, 3>(M, work, Hp, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, f->padlo,
-                                  static_cast<const cplx<T>*>(tw2), s);
+                                  static_cast<const cplx<T>*>(tw2), s, st, a[0], a[1], a[2]);
 }
 
 }  // namespace
@@ -589,35 +629,35 @@ bsi_status grid_from_dense(bsi_field* f, const double* dense, hipStream_t s) {
     const unsigned nb = unsigned(std::min<long>((total + 255) / 256, 65535L * 8));
     if (f->desc.coef == BSI_F64)
         hipLaunchKernelGGL(k_from_dense<double>, dim3(nb), dim3(256), 0, s, dense,
-                           static_cast<double*>(f->grid), f->C, f->n[0], f->n[1], f->n[2], f->P[0],
+                           static_cast<double*>(f->grid), f->C, f->gn[0], f->gn[1], f->gn[2], f->P[0],
                            f->P[1], f->P[2], f->pitch2, f->padlo);
     else if (f->desc.coef == BSI_F32)
         hipLaunchKernelGGL(k_from_dense<float>, dim3(nb), dim3(256), 0, s, dense,
-                           static_cast<float*>(f->grid), f->C, f->n[0], f->n[1], f->n[2], f->P[0],
+                           static_cast<float*>(f->grid), f->C, f->gn[0], f->gn[1], f->gn[2], f->P[0],
                            f->P[1], f->P[2], f->pitch2, f->padlo);
     else
         hipLaunchKernelGGL(k_from_dense<uint16_t>, dim3(nb), dim3(256), 0, s, dense,
-                           static_cast<uint16_t*>(f->grid), f->C, f->n[0], f->n[1], f->n[2], f->P[0],
+                           static_cast<uint16_t*>(f->grid), f->C, f->gn[0], f->gn[1], f->gn[2], f->P[0],
                            f->P[1], f->P[2], f->pitch2, f->padlo);
     BSI_HIP(hipGetLastError());
     return BSI_OK;
 }
 
 bsi_status grid_to_dense(const bsi_field* f, double* dense, hipStream_t s) {
-    const long total = long(f->C) * f->n[0] * f->n[1] * f->n[2];
+    const long total = long(f->C) * f->gn[0] * f->gn[1] * f->gn[2];
     const unsigned nb = unsigned(std::min<long>((total + 255) / 256, 65535L * 8));
     if (f->desc.coef == BSI_F64)
         hipLaunchKernelGGL(k_to_dense<double>, dim3(nb), dim3(256), 0, s,
-                           static_cast<const double*>(f->grid), dense, f->C, f->n[0], f->n[1], f->n[2],
+                           static_cast<const double*>(f->grid), dense, f->C, f->gn[0], f->gn[1], f->gn[2],
                            f->P[1], f->pitch2, f->padlo);
     else if (f->desc.coef == BSI_F32)
         hipLaunchKernelGGL(k_to_dense<float>, dim3(nb), dim3(256), 0, s,
-                           static_cast<const float*>(f->grid), dense, f->C, f->n[0], f->n[1], f->n[2],
+                           static_cast<const float*>(f->grid), dense, f->C, f->gn[0], f->gn[1], f->gn[2],
                            f->P[1], f->pitch2, f->padlo);
     else
         hipLaunchKernelGGL(k_to_dense<uint16_t>, dim3(nb), dim3(256), 0, s,
-                           static_cast<const uint16_t*>(f->grid), dense, f->C, f->n[0], f->n[1],
-                           f->n[2], f->P[1], f->pitch2, f->padlo);
+                           static_cast<const uint16_t*>(f->grid), dense, f->C, f->gn[0], f->gn[1],
+                           f->gn[2], f->P[1], f->pitch2, f->padlo);
     BSI_HIP(hipGetLastError());
     return BSI_OK;
 }

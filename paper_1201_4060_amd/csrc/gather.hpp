@@ -587,11 +587,12 @@ __device__ __forceinline__ AT widen(CT v) {
     else return AT(v);
 }
 
-// w_j(t) = sum_i M[j][i] t^i and w'_j(t) = sum_i M1[j][i] t^i (Horner), M from
-// the Section 7 general formula at compile time.
-template <int N, typename AT>
+// w_j(t) = sum_i M[j][i] t^i and w'_j(t) = sum_i M1[j][i] t^i (Horner), with
+// the matrices of a compile-time table (M from the Section 7 general formula
+// for the B-spline).
+template <int N, typename AT, typename Tab = BSpline<N>>
 __device__ __forceinline__ void bspline_weights(AT t, AT* w, AT* wd) {
-    constexpr BSpline<N> B{};
+    constexpr Tab B{};
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         AT acc = AT(B.M[j][N - 1]);
@@ -602,6 +603,24 @@ __device__ __forceinline__ void bspline_weights(AT t, AT* w, AT* wd) {
 #pragma unroll
         for (int i = N - 3; i >= 0; --i) dacc = dacc * t + AT(B.M1[j][i]);
         wd[j] = dacc;
+    }
+}
+
+// The method's weights (Section 2: w = M tbar, w' = M^(1) tbar): the B-spline
+// (the paper's method), Lagrange (N = 2: linear) or, for N = 4, cubic Hermite.
+// `basis` is the same for every lane of a launch.
+template <int N, typename AT>
+__device__ __forceinline__ void basis_weights(int basis, AT t, AT* w, AT* wd) {
+    if (basis == BSI_BASIS_LAGRANGE) {
+        bspline_weights<N, AT, LagrangeM<N>>(t, w, wd);
+    } else {
+        if constexpr (N == 4) {
+            if (basis == BSI_BASIS_HERMITE) {
+                bspline_weights<4, AT, HermiteM>(t, w, wd);
+                return;
+            }
+        }
+        bspline_weights<N, AT>(t, w, wd);
     }
 }
 
@@ -623,6 +642,8 @@ struct GatherArgs {
     int xcd_remap;
     uint32_t nbuckets_finite;
     uint32_t tiles_per_group;
+    int basis;   // bsi_basis of the field
+    int cs;      // stored grid entries per cell along an axis: 1, or 2 for Hermite (direct gather only)
 };
 
 __device__ __forceinline__ long logical_block(int remap) {
@@ -662,7 +683,7 @@ __device__ __forceinline__ bool particle_setup_x(const GatherArgs& a, const doub
     if (!ok) return false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        bspline_weights<N, AT>(AT(t[d]), w[d], wd[d]);
+        basis_weights<N, AT>(a.basis, AT(t[d]), w[d], wd[d]);
         const AT s = AT(ih[d]);
 #pragma unroll
         for (int k = 0; k < N; ++k) wd[d][k] *= s;
@@ -963,8 +984,8 @@ __device__ __forceinline__ void direct_eval(const GatherArgs& a, long j, bool st
             atomicAdd(a.nonfinite, 1ull);
         }
     } else {
-        const CT* base = static_cast<const CT*>(a.grid) + (long(cell[0]) * a.P1 + cell[1]) * a.pitch2 +
-                         long(cell[2]) * C;
+        const CT* base = static_cast<const CT*>(a.grid) + (long(a.cs * cell[0]) * a.P1 + a.cs * cell[1]) * a.pitch2 +
+                         long(a.cs * cell[2]) * C;
         const long rowA = long(a.P1) * a.pitch2;
         const long rowB = a.pitch2;
         Partial<AT, C> lo, hi;

@@ -466,6 +466,8 @@ void launch_hess_ct(int N, int C, unsigned nb, hipStream_t s, const HessArgs& a)
 
 bsi_status hessian_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad, void* hess,
                        hipStream_t s) {
+    BSI_CHECK(f->basis == BSI_BASIS_BSPLINE && (f->N == 4 || f->N == 6), BSI_E_UNSUPPORTED,
+              "second derivatives are implemented for B-spline fields of orders 4 and 6");
     if (P == 0) return BSI_OK;
     // binned by Morton tiles of 8 cells (at least n/256, so that the bucket
     // table has at most 2^24 entries), for locality of the stencil reads

@@ -7,6 +7,8 @@
 // evaluated here:
 //   INTERP  c = 1 / S_N(kappa)                      (1 / F_D[B_D](k))
 //   L2OPT   c = sinc^N(kappa) / S_2N(kappa)         (F[B] / sum_i F[B](kappa+i)^2)
+//   NONE    c = 1                                   (grid values: Lagrange, linear, Hermite)
+// and, for the Hermite derivative fields, the real factor 2 pi k'/n of d/ds.
 #include <cmath>
 
 #include "common.hpp"
@@ -33,7 +35,14 @@ double lattice_sum(int M, long long ks, int n) {
 void prefilter_table(int n, int order, int variant, double* out) {
     for (int k = 0; k < n; ++k) {
         const long long ks = (k <= n / 2) ? k : k - n;
-        if (variant == BSI_PREFILTER_INTERP) {
+        if (variant == BSI_PREFILTER_NONE) {
+            out[k] = 1.0;
+        } else if (variant == DERIVATIVE_TABLE) {
+            // d/ds of exp(2 pi i ks s / n) in grid units is i 2 pi ks / n times
+            // it: the real factor here, i applied by the FFT's first pass; the
+            // Nyquist index of a real field has no derivative
+            out[k] = (2 * ks == n) ? 0.0 : 2.0 * M_PI * double(ks) / double(n);
+        } else if (variant == BSI_PREFILTER_INTERP) {
             out[k] = 1.0 / lattice_sum(order, ks, n);
         } else {
             double sinc = 1.0;
