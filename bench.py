@@ -43,7 +43,8 @@ NCOMP = 3
 ORDERS = (4, 6)
 P = 1_000_000
 FIELD_SEED, POS_SEED = 1, 101
-STAGES = ("fft_axis0", "fft_axis1", "fft_c2r", "bin_count", "bin_scan", "bin_scatter", "gather")
+STAGES = ("fft_axis0", "fft_axis1", "fft_c2r", "bin_count", "bin_scan", "bin_scatter", "bin_items", "gather")
+EVAL_STAGES = ("bin_count", "bin_scan", "bin_scatter", "bin_items", "gather")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256cube_x3_f32_orders4_6_1e6.md")
 KERNEL_SOURCES = {"gather": ["eval.hip", "gather.hpp", "common.hpp"], "fft": ["fft.hip", "common.hpp"]}
 
@@ -399,8 +400,7 @@ def form_plain(args):
     # alone (binning + gather, stage times) and the prefilter alone
     per_order = {}
     for o in ORDERS:
-        ev = sum(stages[f"{st}@N{o}"]["avg_us"] for st in ("bin_count", "bin_scan", "bin_scatter", "gather")
-                 if f"{st}@N{o}" in stages)
+        ev = sum(stages[f"{st}@N{o}"]["avg_us"] for st in EVAL_STAGES if f"{st}@N{o}" in stages)
         pf = sum(stages[f"{st}@N{o}"]["avg_us"] for st in ("fft_axis0", "fft_axis1", "fft_c2r")
                  if f"{st}@N{o}" in stages)
         per_order[f"N{o}"] = {"eval_us": round(ev, 1), "eval_points_per_s": round(P / (ev * 1e-6), 1),
@@ -673,7 +673,8 @@ def form_precision(args):
             alg[key] = gather_bytes(Pp, C, U, cbytes[k], obytes[k])
         else:
             alg[key] = fft_bytes(st, n, C, N, grid_bytes=cbytes[k], work_bytes=16 if k == "f64" else 8)
-    fma_peak = {"f32": FMA_PEAK_PER_S, "bf16": FMA_PEAK_PER_S, "f64": FMA_PEAK_PER_S / 2}
+    # FP64 vector FMA runs at the unpacked FP32 rate on this chip (78.6 TFLOP/s)
+    fma_peak = {"f32": FMA_PEAK_PER_S, "bf16": FMA_PEAK_PER_S, "f64": FMA_PEAK_PER_S}
 
     def gather_entry(k):
         key = f"gather@{k}"
@@ -688,7 +689,7 @@ def form_precision(args):
     roofline = gather_entry("f32")
     legs = {}
     for k, _, _ in kinds:
-        ev = sum(stages[f"{st}@{k}"]["avg_us"] for st in ("bin_count", "bin_scan", "bin_scatter", "gather"))
+        ev = sum(stages[f"{st}@{k}"]["avg_us"] for st in EVAL_STAGES if f"{st}@{k}" in stages)
         pf = sum(stages[f"{st}@{k}"]["avg_us"] for st in ("fft_axis0", "fft_axis1", "fft_c2r"))
         legs[k] = {"points_per_s": round(Pp / sps[k], 1), "ms_per_step": round(sps[k] * 1e3, 4),
                    "ms_per_step_percentiles": pct[k], "prefilter_us": round(pf, 1), "eval_us": round(ev, 1),
@@ -730,7 +731,11 @@ def form_precision(args):
     for k, _, _ in kinds:
         fields[k].close()
         ctxs[k].close()
-    del outs, uhat, pos, uhat_np
+    del outs
+    methods = None
+    if args.methods_in_default:
+        methods = methods_legs(bsi, uhat, pos, n, C, args)
+    del uhat, pos, uhat_np
     torch.cuda.empty_cache()
     config = {"workload": "512^3 x3 divergence-free Kolmogorov field, order 6, 1e7 clustered particles "
                           "(5e6 uniform + 100 Gaussian blobs of 5e4, sigma 0.1); step = prefilter (FP64 symbol "
@@ -739,9 +744,83 @@ def form_precision(args):
               "n": n, "ncomp": C, "order": N, "particles": Pp, "grid_dtype": "f32", "spectrum_dtype": "c128",
               "parallelism": "single GPU"}
     extra = {"legs": legs, "copy_GBs": round(copy_gbs, 1)}
+    if methods is not None:
+        extra["methods"] = methods
     if args.serve_in_default:
         extra["serving"] = serve_summary(args)
     return base_line(args, Pp / sps["f32"], "points/s", sps["f32"], "f32", config, roofline, cpu, **extra)
+
+
+# ---------------------------------------------------------- methods leg ---
+
+# (name, basis, order, prefilter) of the four methods of Table 2 (and the
+# order-6 B-spline of the headline), all on FP32 grids
+METHODS = (("bspline4", "BSPLINE", 4, "L2OPT"), ("bspline6", "BSPLINE", 6, "L2OPT"),
+           ("lagrange4", "LAGRANGE", 4, "NONE"), ("lagrange6", "LAGRANGE", 6, "NONE"),
+           ("linear", "LAGRANGE", 2, "NONE"), ("hermite", "HERMITE", 4, "NONE"))
+
+
+def methods_legs(bsi, uhat, pos, n, C, args):
+    """The methods Table 2 compares, on the same spectrum and particles, FP32
+    grids: per method the prefilter (B-spline: one inverse FFT per component;
+    Lagrange and linear: one FFT with c = 1; Hermite: eight, one per
+    derivative field) and the evaluation (binning + gather), timed by the
+    library's stage events over `steps` steps of set_spectrum + eval."""
+    import torch
+    P_ = pos.shape[0]
+    ctx = bsi.Context(0)
+    out = {}
+    steps = max(3, args.steps // 2)
+    for name, basis, N, pf in METHODS:
+        f = bsi.Field(ctx, n, C, N, bsi.BSI_F32, prefilter=getattr(bsi, "BSI_PREFILTER_" + pf),
+                      basis=getattr(bsi, "BSI_BASIS_" + basis))
+        u = torch.empty((P_, C), dtype=torch.float32, device=pos.device)
+        g = torch.empty((P_, C, 3), dtype=torch.float32, device=pos.device)
+
+        def step():
+            f.set_spectrum(uhat)
+            f.eval(pos, out=(u, g))
+
+        sec = timed_steps(step, 1, steps, [ctx], bsi)
+        st = read_stages(bsi, ctx, name)
+        bsi._bsi.bsi_ctx_set_timing(ctx.handle, False)
+        per = {k.split("@")[0]: v["total_ms"] * 1e3 / steps for k, v in st.items()}
+        pf_us = sum(per.get(s, 0.0) for s in ("fft_axis0", "fft_axis1", "fft_c2r"))
+        ev_us = sum(per.get(s, 0.0) for s in EVAL_STAGES)
+        fft_launches = sum(st[k]["launches"] for k in st if k.split("@")[0] == "fft_c2r") // steps
+        out[name] = {"basis": basis.lower(), "order": N, "prefilter": pf.lower(),
+                     "inverse_ffts_per_component": fft_launches, "grid_bytes": f.nbytes(),
+                     "prefilter_us": round(pf_us, 1), "eval_us": round(ev_us, 1),
+                     "gather_us": round(per.get("gather", 0.0), 1),
+                     "eval_points_per_s": round(P_ / (ev_us * 1e-6), 1),
+                     "ms_per_step": round(sec * 1e3, 4), "points_per_s": round(P_ / sec, 1)}
+        eprint(f"{name}: prefilter {pf_us:.1f} us ({fft_launches} inverse FFTs), eval {ev_us:.1f} us, "
+               f"{sec * 1e3:.3f} ms/step")
+        f.close()
+        del u, g
+    ctx.close()
+    torch.cuda.empty_cache()
+    out["hermite_vs_bspline4_prefilter"] = round(out["hermite"]["prefilter_us"] / out["bspline4"]["prefilter_us"], 2)
+    out["note"] = ("FP32 grids, same spectrum and particles as the headline; inverse FFTs counted per "
+                   "component (one launch of each pass transforms all components); stage times are per step")
+    return out
+
+
+def form_methods(args):
+    """The methods leg alone on the 512^3 x3 workload (see methods_legs)."""
+    import torch
+    import synth
+    import paper_1201_4060_amd as bsi
+    n, C = PREC_N, PREC_C
+    uhat = torch.from_numpy(synth.kolmogorov_spectrum(n, C, seed=PREC_FIELD_SEED)).to("cuda:0")
+    pos = torch.from_numpy(synth.clustered_positions(5_000_000, 100, 50_000, 0.1, seed=PREC_POS_SEED)).to("cuda:0")
+    m = methods_legs(bsi, uhat, pos, n, C, args)
+    b = m["bspline4"]
+    config = {"workload": "512^3 x3 divergence-free Kolmogorov field, 1e7 clustered particles; the methods of "
+                          "Table 2 on FP32 grids; value: the order-4 B-spline step",
+              "n": n, "ncomp": C, "particles": pos.shape[0], "parallelism": "single GPU"}
+    return base_line(args, b["points_per_s"], "points/s", b["ms_per_step"] * 1e-3, "f32", config, None, None,
+                     methods=m)
 
 
 # ------------------------------------------------------------ batch form ---
@@ -1033,7 +1112,7 @@ def copy_calibration(steps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--form", choices=("plain", "precision", "batch", "serve", "hessian", "copy"),
+    ap.add_argument("--form", choices=("plain", "precision", "batch", "serve", "hessian", "methods", "copy"),
                     default="precision")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -1051,6 +1130,8 @@ def main():
                     help="requests per rate point of the serving leg attached to the precision form")
     ap.add_argument("--no-serve", dest="serve_in_default", action="store_false",
                     help="precision form: skip the attached serving leg")
+    ap.add_argument("--no-methods", dest="methods_in_default", action="store_false",
+                    help="precision form: skip the attached methods leg (Table 2's methods timed)")
     ap.add_argument("--cpu-workers", type=int, default=16,
                     help="host processes of the CPU oracle baseline (capped at the CPU count)")
     ap.add_argument("--cpu-per-worker", type=int, default=25000,
@@ -1069,7 +1150,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     form = {"plain": form_plain, "precision": form_precision, "batch": form_batch, "serve": form_serve,
-            "hessian": form_hessian}
+            "hessian": form_hessian, "methods": form_methods}
     print(json.dumps(form[args.form](args)), flush=True)
 
 

@@ -97,16 +97,21 @@ typedef struct bsi_field_desc {
 typedef struct bsi_eval_config {
     int32_t sort_tile;   /* cells per Morton tile edge for particle binning; 0 = no binning */
     int32_t block;       /* threads per workgroup of the gather kernel (64..1024, multiple of 64) */
-    int32_t xcd_remap;   /* 1 = map consecutive binned particle blocks onto one XCD            */
+    int32_t xcd_remap;   /* 1 = map consecutive binned particle blocks onto one XCD (tiled
+                            gather: each XCD's workgroups start on their own range of tiles)   */
     int32_t variant;     /* 0 = LDS-tiled gather when sort_tile > 0 and the tile fits (sizes 4, 6,
                             8, 12, 16 whose block is at most 64 KB of LDS and whose origin is
                             16-byte aligned); otherwise, and for 1, one thread per particle
                             reading the grid directly */
-    int32_t tiles_per_group; /* consecutive Morton tiles walked by one tiled workgroup (0 = 4) */
+    int32_t tiles_per_group; /* persistent batch gather: consecutive Morton tiles of one item
+                                walked by one workgroup (0 = 4); unused by single-field evaluation */
     int32_t tile_block;      /* threads per workgroup of the tiled gather with 8^3-cell tiles:
                                 0 or 64 = one wavefront per tile, 256 = four wavefronts share a
                                 tile (dense tiles); other tile sizes have a fixed block */
-    int32_t reserved[2];     /* must be 0 */
+    int32_t item_rounds;     /* tiled gather: a crowded tile is cut into work items of at most
+                                item_rounds x (threads per workgroup) particles, shared out
+                                among the workgroups (0 = 4) */
+    int32_t reserved[1];     /* must be 0 */
 } bsi_eval_config;
 
 typedef struct bsi_ctx bsi_ctx;

@@ -32,7 +32,7 @@ class EvalConfig(ctypes.Structure):
     _fields_ = [("sort_tile", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("tiles_per_group", ctypes.c_int32), ("tile_block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("item_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class ServerConfig(ctypes.Structure):

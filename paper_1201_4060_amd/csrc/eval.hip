@@ -66,19 +66,68 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
     direct_eval<N, CT, C, GRAD>(a, j);
 }
 
-// LDS-tiled variant: one workgroup of B threads walks `tiles_per_group`
-// consecutive Morton tiles (T^3 cells each), skipping empty ones.
+// Index of the next ITEM_TAKE items of range x, requested by the workgroup's
+// first lane (the value is valid in that lane only; item_take_finish makes it
+// uniform).
+__device__ __forceinline__ uint32_t item_take_issue(const GatherArgs& a, uint32_t x) {
+    uint32_t v = 0;
+    if (threadIdx.x == 0) v = atomicAdd(a.ctl + ITEM_CTL_STRIDE * (x + 1), ITEM_TAKE);
+    return v;
+}
+
+template <int B>
+__device__ __forceinline__ uint32_t item_take_finish(uint32_t v, uint32_t* sh) {
+    if constexpr (B == 64) {
+        return __builtin_amdgcn_readfirstlane(v);
+    } else {
+        if (threadIdx.x == 0) *sh = v;
+        __syncthreads();
+        const uint32_t r = __builtin_amdgcn_readfirstlane(*sh);
+        __syncthreads();
+        return r;
+    }
+}
+
+// LDS-tiled variant: persistent workgroups of B threads evaluate work items
+// (pieces of Morton tiles of T^3 cells, k_items).  A workgroup takes the items
+// of its home range in order, ITEM_TAKE at a time through the range's
+// counter, then those of the other ranges, and ends when every range is
+// exhausted; the next take is requested before the last item of the current
+// one is evaluated.  Home range: blockIdx % ITEM_RANGES with xcd_remap
+// (workgroups are dispatched to the XCDs in turn), 0 for every workgroup
+// without.  Consecutive items of one tile reuse the tile's block in LDS.
+// (the LDS block limits FP64 and padded FP32 blocks to about one wavefront
+// per SIMD: the registers are not the limit there)
 template <int N, typename CT, int C, bool GRAD, int T, int B>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(sizeof(CT) == 8 ? 1 : 2))) void k_gather_tiled(GatherArgs a) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
+    sizeof(CT) == 8 || padded_points<CT, C>() ? 1 : 2))) void k_gather_tiled(GatherArgs a) {
     __shared__ u32x4 tile_v[tile_lds_bytes<N, CT, C, T, B>() / 16];
-    const uint32_t nbt = a.nbuckets_finite + 1;
-    const uint32_t b0 = uint32_t(logical_block(a.xcd_remap)) * a.tiles_per_group;
-    const uint32_t b1 = min(b0 + a.tiles_per_group, nbt);
-    // the tile index is made wave-uniform so that the loop (which holds
-    // workgroup barriers) is scalar
-    for (uint32_t cur = __builtin_amdgcn_readfirstlane(next_tile(a, b0, b1)); cur < b1;
-         cur = __builtin_amdgcn_readfirstlane(next_tile(a, cur + 1, b1)))
-        tile_eval<N, CT, C, GRAD, T, B>(a, cur, tile_v);
+    __shared__ uint32_t taken;
+    // every value that steers a loop or branch holding a barrier is made
+    // wave-uniform explicitly, so that those loops are scalar
+    const uint32_t W = __builtin_amdgcn_readfirstlane(a.ctl[0]);
+    const uint32_t home = a.xcd_remap ? uint32_t(blockIdx.x) % ITEM_RANGES : 0u;
+    uint32_t prev = 0xffffffffu;  // bucket whose block the LDS holds
+    for (uint32_t r = 0; r < ITEM_RANGES; ++r) {
+        const uint32_t x = (home + r) % ITEM_RANGES;
+        const uint32_t lo = item_range_begin(W, x);
+        const uint32_t hi = item_range_begin(W, x + 1);
+        uint32_t i = item_take_finish<B>(item_take_issue(a, x), &taken);
+        while (lo + i < hi) {
+            const uint32_t m = min(ITEM_TAKE, hi - lo - i);
+            uint32_t next = 0;
+            for (uint32_t k = 0; k < m; ++k) {
+                const u32x4 it = a.items[lo + i + k];
+                const uint32_t cur = __builtin_amdgcn_readfirstlane(it.x);
+                const uint32_t start = __builtin_amdgcn_readfirstlane(it.y);
+                const uint32_t count = __builtin_amdgcn_readfirstlane(it.z);
+                if (k + 1 == m) next = item_take_issue(a, x);
+                bucket_eval<N, CT, C, GRAD, T, B>(a, cur, count, start, tile_v, cur != prev);
+                prev = cur;
+            }
+            i = item_take_finish<B>(next, &taken);
+        }
+    }
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -134,8 +183,23 @@ constexpr int tile_block() {
     return TileGeom<N, CT, C, T>::SLOTS >= 3072 ? 256 : 64;
 }
 
+// The tiled gather runs as many workgroups as can be resident at once (its
+// occupancy, asked once per instance, on every CU).
+template <int N, typename CT, int C, bool GRAD, int T, int B>
+void launch_tiled_kernel(const GatherArgs& ga, int num_cus, hipStream_t s) {
+    auto k = k_gather_tiled<N, CT, C, GRAD, T, B>;
+    static unsigned nb = 0;
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k, B, 0) != hipSuccess || v < 1) v = 1;
+        nb = unsigned(v);
+    });
+    hipLaunchKernelGGL(k, dim3(nb * unsigned(std::max(num_cus, 1))), dim3(B), 0, s, ga);
+}
+
 template <int N, typename CT, int C, int T>
-bool launch_tiled_T(const GatherArgs& ga, bool grad, bool wide, unsigned nb, hipStream_t s) {
+bool launch_tiled_T(const GatherArgs& ga, bool grad, bool wide, int num_cus, hipStream_t s) {
     if constexpr (!tile_ok<N, CT, C, T>()) {
         return false;
     } else {
@@ -143,46 +207,72 @@ bool launch_tiled_T(const GatherArgs& ga, bool grad, bool wide, unsigned nb, hip
         if constexpr (T == 8 && B == 64) {
             // dense 8^3 tiles: four wavefronts share one LDS block
             if (wide) {
-                if (grad)
-                    hipLaunchKernelGGL((k_gather_tiled<N, CT, C, true, T, 256>), dim3(nb), dim3(256), 0, s, ga);
-                else
-                    hipLaunchKernelGGL((k_gather_tiled<N, CT, C, false, T, 256>), dim3(nb), dim3(256), 0, s, ga);
+                if (grad) launch_tiled_kernel<N, CT, C, true, T, 256>(ga, num_cus, s);
+                else launch_tiled_kernel<N, CT, C, false, T, 256>(ga, num_cus, s);
                 return true;
             }
         }
-        if (grad)
-            hipLaunchKernelGGL((k_gather_tiled<N, CT, C, true, T, B>), dim3(nb), dim3(B), 0, s, ga);
-        else
-            hipLaunchKernelGGL((k_gather_tiled<N, CT, C, false, T, B>), dim3(nb), dim3(B), 0, s, ga);
+        if (grad) launch_tiled_kernel<N, CT, C, true, T, B>(ga, num_cus, s);
+        else launch_tiled_kernel<N, CT, C, false, T, B>(ga, num_cus, s);
         return true;
     }
 }
 
+// threads per workgroup of the tiled gather for this field and tile (0 if no
+// tiled instance)
+template <int N, typename CT, int C, int T>
+constexpr int tiled_block_T(bool wide) {
+    if constexpr (!tile_ok<N, CT, C, T>()) return 0;
+    else return (T == 8 && tile_block<N, CT, C, T>() == 64 && wide) ? 256 : tile_block<N, CT, C, T>();
+}
+
 template <int N, typename CT, int C>
-bool launch_tiled_c(int T, const GatherArgs& ga, bool grad, bool wide, unsigned nb, hipStream_t s) {
+bool launch_tiled_c(int T, const GatherArgs& ga, bool grad, bool wide, int num_cus, hipStream_t s) {
     switch (T) {
-        case 4: return launch_tiled_T<N, CT, C, 4>(ga, grad, wide, nb, s);
-        case 6: return launch_tiled_T<N, CT, C, 6>(ga, grad, wide, nb, s);
-        case 8: return launch_tiled_T<N, CT, C, 8>(ga, grad, wide, nb, s);
-        case 12: return launch_tiled_T<N, CT, C, 12>(ga, grad, wide, nb, s);
-        case 16: return launch_tiled_T<N, CT, C, 16>(ga, grad, wide, nb, s);
+        case 4: return launch_tiled_T<N, CT, C, 4>(ga, grad, wide, num_cus, s);
+        case 6: return launch_tiled_T<N, CT, C, 6>(ga, grad, wide, num_cus, s);
+        case 8: return launch_tiled_T<N, CT, C, 8>(ga, grad, wide, num_cus, s);
+        case 12: return launch_tiled_T<N, CT, C, 12>(ga, grad, wide, num_cus, s);
+        case 16: return launch_tiled_T<N, CT, C, 16>(ga, grad, wide, num_cus, s);
         default: return false;
     }
 }
 
 template <typename CT>
-bool launch_tiled_ct(int N, int C, int T, const GatherArgs& ga, bool grad, bool wide, unsigned nb,
+bool launch_tiled_ct(int N, int C, int T, const GatherArgs& ga, bool grad, bool wide, int num_cus,
                      hipStream_t s) {
     if (N == 2) {   // linear: 8^3-cell tiles only
         if (T != 8) return false;
-        return C == 1 ? launch_tiled_T<2, CT, 1, 8>(ga, grad, wide, nb, s)
-                      : launch_tiled_T<2, CT, 3, 8>(ga, grad, wide, nb, s);
+        return C == 1 ? launch_tiled_T<2, CT, 1, 8>(ga, grad, wide, num_cus, s)
+                      : launch_tiled_T<2, CT, 3, 8>(ga, grad, wide, num_cus, s);
     }
     if (N == 4)
-        return C == 1 ? launch_tiled_c<4, CT, 1>(T, ga, grad, wide, nb, s)
-                      : launch_tiled_c<4, CT, 3>(T, ga, grad, wide, nb, s);
-    return C == 1 ? launch_tiled_c<6, CT, 1>(T, ga, grad, wide, nb, s)
-                  : launch_tiled_c<6, CT, 3>(T, ga, grad, wide, nb, s);
+        return C == 1 ? launch_tiled_c<4, CT, 1>(T, ga, grad, wide, num_cus, s)
+                      : launch_tiled_c<4, CT, 3>(T, ga, grad, wide, num_cus, s);
+    return C == 1 ? launch_tiled_c<6, CT, 1>(T, ga, grad, wide, num_cus, s)
+                  : launch_tiled_c<6, CT, 3>(T, ga, grad, wide, num_cus, s);
+}
+
+template <int N, typename CT, int C>
+int tiled_block_c(int T, bool wide) {
+    switch (T) {
+        case 4: return tiled_block_T<N, CT, C, 4>(wide);
+        case 6: return tiled_block_T<N, CT, C, 6>(wide);
+        case 8: return tiled_block_T<N, CT, C, 8>(wide);
+        case 12: return tiled_block_T<N, CT, C, 12>(wide);
+        case 16: return tiled_block_T<N, CT, C, 16>(wide);
+        default: return 0;
+    }
+}
+
+template <typename CT>
+int tiled_block_ct(int N, int C, int T, bool wide) {
+    if (N == 2) {
+        if (T != 8) return 0;
+        return C == 1 ? tiled_block_T<2, CT, 1, 8>(wide) : tiled_block_T<2, CT, 3, 8>(wide);
+    }
+    if (N == 4) return C == 1 ? tiled_block_c<4, CT, 1>(T, wide) : tiled_block_c<4, CT, 3>(T, wide);
+    return C == 1 ? tiled_block_c<6, CT, 1>(T, wide) : tiled_block_c<6, CT, 3>(T, wide);
 }
 
 template <int N, typename CT, int C>
@@ -281,10 +371,41 @@ static int effective_tile(const bsi_field* f, const bsi_eval_config& cfg) {
     return std::max(cfg.sort_tile, (nmax + 255) / 256);
 }
 
+// Threads per workgroup of the tiled gather for field f, tile and config (0:
+// no tiled instance, the direct gather runs).
+static int tiled_block(const bsi_field* f, int tile, const bsi_eval_config& cfg) {
+    if (tile == 0 || cfg.variant != 0 || !tiled_supported(f, tile)) return 0;
+    const bool wide = cfg.tile_block == 256;
+    if (f->desc.coef == BSI_F64) return tiled_block_ct<double>(f->N, f->C, tile, wide);
+    if (f->desc.coef == BSI_F32) return tiled_block_ct<float>(f->N, f->C, tile, wide);
+    return tiled_block_ct<uint16_t>(f->N, f->C, tile, wide);
+}
+
+// Work items of the tiled gather after the binning's arrays: at most one per
+// non-empty bucket plus one per `chunk` particles, 16 bytes each, then the
+// control words.
+struct ItemLayout {
+    size_t items, ctl, bytes;
+    uint32_t chunk;
+};
+
+static ItemLayout item_layout(const bsi_field* f, long P, int tile, const bsi_eval_config& cfg, size_t base) {
+    ItemLayout l{};
+    const int B = tiled_block(f, tile, cfg);
+    l.items = l.ctl = l.bytes = base;
+    if (B == 0) return l;
+    l.chunk = uint32_t(B) * uint32_t(cfg.item_rounds > 0 ? cfg.item_rounds : 4);
+    const size_t cap = bin_bucket_count(f, tile) + 1 + size_t(P) / l.chunk + 1;
+    l.items = (base + 15) / 16 * 16;
+    l.ctl = l.items + cap * 16;
+    l.bytes = l.ctl + ITEM_CTL_WORDS * sizeof(uint32_t);
+    return l;
+}
+
 size_t eval_ws_bytes(const bsi_field* f, int64_t P, const bsi_eval_config& cfg) {
     const int tile = effective_tile(f, cfg);
     if (tile == 0 || P == 0) return 0;
-    return bin_layout(f, P, tile).bytes;
+    return item_layout(f, P, tile, cfg, bin_layout(f, P, tile).bytes).bytes;
 }
 
 bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
@@ -295,12 +416,14 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
               "eval block must be 64, 128, 192 or 256");
     BSI_CHECK(cfg.tile_block == 0 || cfg.tile_block == 64 || cfg.tile_block == 256, BSI_E_INVAL,
               "tile_block must be 0, 64 or 256");
+    BSI_CHECK(cfg.item_rounds >= 0 && cfg.item_rounds <= 1024, BSI_E_INVAL, "item_rounds must be 0..1024");
     const uint32_t* perm = nullptr;
     const double* pos_sorted = nullptr;
     const uint32_t* hist = nullptr;
     const uint32_t* offs = nullptr;
     const int tile = effective_tile(f, cfg);
     size_t nbf = 0;
+    ItemLayout il{};
     if (tile > 0) {
         BSI_CHECK(ws != nullptr && reinterpret_cast<uintptr_t>(ws) % 16 == 0, BSI_E_INVAL,
                   "binned evaluation needs a 16-byte aligned workspace");
@@ -316,6 +439,7 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
         hist = hs;
         offs = os;
         nbf = bin_bucket_count(f, tile);
+        il = item_layout(f, P, tile, cfg, l.bytes);
     }
     GatherArgs ga;
     ga.grid = f->grid;
@@ -342,19 +466,32 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
     ga.nbuckets_finite = uint32_t(nbf);
     ga.basis = f->basis;
     ga.cs = f->cs;
+    ga.items = nullptr;
+    ga.ctl = nullptr;
     const bool g = grad != nullptr;
-    StageTimer tm(f->ctx, "gather", s);
-    const bool tiled = perm && cfg.variant == 0 && tiled_supported(f, tile);
+    const bool tiled = perm && il.chunk > 0;
     if (tiled) {
-        const unsigned nb = unsigned((nbf + 1 + ga.tiles_per_group - 1) / ga.tiles_per_group);
+        char* w = static_cast<char*>(ws);
+        ga.items = reinterpret_cast<const u32x4*>(w + il.items);
+        ga.ctl = reinterpret_cast<uint32_t*>(w + il.ctl);
+        {
+            StageTimer tm(f->ctx, "bin_items", s);
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ga.ctl, long(ITEM_CTL_WORDS), 0u);
+            const long nb = long(nbf) + 1;
+            hipLaunchKernelGGL(k_items, dim3(unsigned((nb + SCAN_CHUNK - 1) / SCAN_CHUNK)), dim3(SCAN_BLOCK), 0, s,
+                               hist, offs, nb, il.chunk, reinterpret_cast<u32x4*>(w + il.items), ga.ctl);
+        }
+        StageTimer tm(f->ctx, "gather", s);
         bool ok = false;
         // tile_block 256 asks for four wavefronts per 8^3 tile (dense tiles)
         const bool wide = cfg.tile_block == 256;
-        if (f->desc.coef == BSI_F64) ok = launch_tiled_ct<double>(f->N, f->C, tile, ga, g, wide, nb, s);
-        else if (f->desc.coef == BSI_F32) ok = launch_tiled_ct<float>(f->N, f->C, tile, ga, g, wide, nb, s);
-        else ok = launch_tiled_ct<uint16_t>(f->N, f->C, tile, ga, g, wide, nb, s);
+        const int ncu = f->ctx->num_cus;
+        if (f->desc.coef == BSI_F64) ok = launch_tiled_ct<double>(f->N, f->C, tile, ga, g, wide, ncu, s);
+        else if (f->desc.coef == BSI_F32) ok = launch_tiled_ct<float>(f->N, f->C, tile, ga, g, wide, ncu, s);
+        else ok = launch_tiled_ct<uint16_t>(f->N, f->C, tile, ga, g, wide, ncu, s);
         BSI_CHECK(ok, BSI_E_UNSUPPORTED, "no tiled gather instance for this tile size");
     } else {
+        StageTimer tm(f->ctx, "gather", s);
         const unsigned nb = unsigned((P + block - 1) / block);
         if (f->desc.coef == BSI_F64) launch_gather_ct<double>(f->N, f->C, ga, g, nb, block, s);
         else if (f->desc.coef == BSI_F32) launch_gather_ct<float>(f->N, f->C, ga, g, nb, block, s);

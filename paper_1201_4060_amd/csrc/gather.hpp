@@ -151,6 +151,7 @@ static __global__ void k_fill_u32(uint32_t* p, long n, uint32_t v) {
 // 16 bytes as a native vector (loads and stores of it are single instructions,
 // never aggregate copies) and a load of it from global memory.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) u32x4 global_u32x4;
 
 __device__ __forceinline__ u32x4 load_global16(const u32x4* p) {
@@ -644,6 +645,8 @@ struct GatherArgs {
     uint32_t tiles_per_group;
     int basis;   // bsi_basis of the field
     int cs;      // stored grid entries per cell along an axis: 1, or 2 for Hermite (direct gather only)
+    const u32x4* items;  // work items of the tiled kernel: (bucket, first binned slot, count, 0)
+    uint32_t* ctl;       // number of items and the ranges' counters (tiled kernel; ITEM_CTL_WORDS)
 };
 
 __device__ __forceinline__ long logical_block(int remap) {
@@ -758,8 +761,12 @@ __device__ __forceinline__ void contract_plane(AT w0k, AT wd0k, const AT (*w)[N]
 // realigned by a funnel shift per pair of values when used.  The N*C/2 + 1
 // dwords end at most 4 bytes past the row's values, inside the row's padding
 // to whole 16-byte chunks for every tile geometry of the tiled gathers.
-template <int N, typename CT, int C>
+// PS is the LDS pitch of one grid point in elements: C for densely packed
+// rows; 4 for FP32 three-component points held in 16-byte slots, read with one
+// 16-byte LDS read each (element e = point e / 3, component e % 3).
+template <int N, typename CT, int C, int PS = C>
 struct LdsRow {
+    static_assert(PS == C, "padded points: FP32, three components");
     CT raw[N * C];
     __device__ __forceinline__ void load(const CT* r) {
 #pragma unroll
@@ -768,8 +775,18 @@ struct LdsRow {
     __device__ __forceinline__ CT get(int e) const { return raw[e]; }
 };
 
+template <int N>
+struct LdsRow<N, float, 3, 4> {
+    f32x4 pt[N];
+    __device__ __forceinline__ void load(const float* r) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) pt[k] = *reinterpret_cast<const f32x4*>(r + 4 * k);
+    }
+    __device__ __forceinline__ float get(int e) const { return pt[e / 3][e % 3]; }
+};
+
 template <int N, int C>
-struct LdsRow<N, uint16_t, C> {
+struct LdsRow<N, uint16_t, C, C> {
     static_assert((N * C) % 2 == 0, "BF16 rows are read as pairs");
     static constexpr int ND = N * C / 2 + 1;
     uint32_t dw[ND];
@@ -795,13 +812,15 @@ struct LdsRow<N, uint16_t, C> {
 // that the LDS latency of one row hides behind the FMAs of the previous one.
 // Otherwise (rows in global memory) everything is unrolled and left to the
 // compiler.  The arithmetic, and its order, is the same in both forms.
-template <int N, typename CT, typename AT, int C, bool GRAD, int NIA, bool FENCE = false, typename RowFn>
+template <int N, typename CT, typename AT, int C, bool GRAD, int NIA, bool FENCE = false, int PS = C,
+          typename RowFn>
 __device__ __forceinline__ void contract_planes(const AT* w0, const AT* wd0, const AT (*w)[N],
                                                 const AT (*wd)[N], RowFn row, Partial<AT, C>& out) {
+    static_assert(FENCE || PS == C, "rows in global memory are densely packed");
 #pragma unroll
     for (int c = 0; c < C; ++c) out.u[c] = out.g0[c] = out.g1[c] = out.g2[c] = AT(0);
     if constexpr (FENCE) {
-        LdsRow<N, CT, C> buf[2];
+        LdsRow<N, CT, C, PS> buf[2];
         buf[0].load(row(0, 0));
 #pragma unroll
         for (int k = 0; k < NIA; ++k) {
@@ -812,7 +831,7 @@ __device__ __forceinline__ void contract_planes(const AT* w0, const AT* wd0, con
             for (int ib = 0; ib < N; ++ib) {
                 const int r = k * N + ib;
                 if (r + 1 < NIA * N) buf[(r + 1) & 1].load(row((r + 1) / N, (r + 1) % N));
-                const LdsRow<N, CT, C>& cur = buf[r & 1];
+                const LdsRow<N, CT, C, PS>& cur = buf[r & 1];
                 AT tr[C], trd[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) tr[c] = trd[c] = AT(0);
@@ -887,27 +906,41 @@ __device__ __forceinline__ void contract_and_store(const GatherArgs& a, long p, 
     store_sum<AT, C, GRAD>(a, p, lo, hi);
 }
 
+// FP32 three-component blocks hold one grid point per 16-byte LDS slot (the
+// fourth float is spare): a stencil row is then N aligned 16-byte LDS reads
+// wherever it starts, where densely packed 12-byte points need 4-byte reads.
+template <typename CT, int C>
+constexpr bool padded_points() {
+    return sizeof(CT) == 4 && C == 3;
+}
+
 // LDS copy of the (T0+N-1) x (T1+N-1) x (T2+N-1) block of grid points that
-// the particles of a T0 x T1 x T2 cell box read: rows along axis 2, each
-// padded to whole 16-byte chunks.
-template <int N, typename CT, int C, int T0, int T1, int T2>
+// the particles of a T0 x T1 x T2 cell box read: rows along axis 2, either
+// packed densely and padded to whole 16-byte chunks (PAD false), or one
+// 16-byte slot per point (PAD true).
+template <int N, typename CT, int C, int T0, int T1, int T2, bool PAD = padded_points<CT, C>()>
 struct BlockGeom {
+    static_assert(!PAD || padded_points<CT, C>(), "padded points: FP32, three components");
+    static constexpr bool PADDED = PAD;
     static constexpr int R0 = T0 + N - 1;
     static constexpr int R1 = T1 + N - 1;
     static constexpr int R2 = T2 + N - 1;
-    static constexpr int VEC = 16 / int(sizeof(CT));    // elements per 16-byte chunk
-    static constexpr int CH = (R2 * C + VEC - 1) / VEC;  // chunks per row
-    static constexpr int LROW = CH * VEC;                // LDS row pitch (elements)
+    static constexpr int VEC = 16 / int(sizeof(CT));                // elements per 16-byte slot
+    static constexpr int PS = PAD ? VEC : C;                        // LDS pitch of a point (elements)
+    static constexpr int CH = PAD ? R2 : (R2 * C + VEC - 1) / VEC;  // 16-byte slots per row
+    static constexpr int LROW = CH * VEC;                           // LDS row pitch (elements)
     static constexpr int ROWS = R0 * R1;
     static constexpr int SLOTS = ROWS * CH;
     static constexpr int BYTES = SLOTS * 16;
-    // block origins must start on 16-byte boundaries inside a row
-    static constexpr bool ALIGNED = (T2 * C * int(sizeof(CT))) % 16 == 0;
+    // packed rows are copied in 16-byte chunks from the block origin, which
+    // must then start on a 16-byte boundary inside a grid row; padded points
+    // are copied one point (4-byte aligned) per slot
+    static constexpr bool ALIGNED = PAD || (T2 * C * int(sizeof(CT))) % 16 == 0;
 };
 
 // Cubic Morton tiles of T^3 cells.
-template <int N, typename CT, int C, int T>
-using TileGeom = BlockGeom<N, CT, C, T, T, T>;
+template <int N, typename CT, int C, int T, bool PAD = padded_points<CT, C>()>
+using TileGeom = BlockGeom<N, CT, C, T, T, T, PAD>;
 
 
 template <typename AT>
@@ -933,10 +966,13 @@ __device__ __forceinline__ uint32_t next_tile(const GatherArgs& a, uint32_t b, u
 // slots tid, tid + B, ... are copied global -> LDS by the DMA path of the load
 // unit (no registers hold the data), each wavefront's instruction q filling 64
 // consecutive 16-byte slots from its wave-uniform LDS base; only the last step
-// can reach past the block, and its lanes there are masked off.  Rows outside
-// the padded grid (partial blocks only; never read by a particle) load the
-// block origin instead; chunks past a row's end read the next row or the
-// allocation's slack.  Does not wait for the loads.
+// can reach past the block, and its lanes there are masked off.  A packed slot
+// is the row's next 16-byte chunk; a padded slot is the 16 bytes from its
+// point's first element (the point and the first element of the next one).
+// Rows outside the padded grid (partial blocks only; never read by a
+// particle) load the block origin instead; reads past a row's end land in the
+// next row, its pitch padding or the allocation's slack.  Does not wait for
+// the loads.
 template <int N, typename CT, int C, typename G, int B>
 __device__ __forceinline__ void block_dma(const CT* grid, int n0, int n1, int P1, long pitch2, int o0, int o1,
                                           int o2, u32x4* lds) {
@@ -944,9 +980,10 @@ __device__ __forceinline__ void block_dma(const CT* grid, int n0, int n1, int P1
     const int tid = threadIdx.x;
     const int lim0 = n0 + N - 1 - o0;
     const int lim1 = n1 + N - 1 - o1;
-    const u32x4* g = reinterpret_cast<const u32x4*>(grid + (long(o0) * P1 + o1) * pitch2 + long(o2) * C);
-    const int p1v = int(pitch2 / G::VEC);  // row pitch in chunks (offsets inside a block stay < 2^31)
-    const int p0v = P1 * p1v;
+    const CT* g = grid + (long(o0) * P1 + o1) * pitch2 + long(o2) * C;
+    // offsets inside a block stay < 2^31 elements
+    const int p1e = int(pitch2);
+    const int p0e = P1 * p1e;
     const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
 #pragma unroll
     for (int q = 0; q < PERB; ++q) {
@@ -956,8 +993,9 @@ __device__ __forceinline__ void block_dma(const CT* grid, int n0, int n1, int P1
         const int r0 = row / G::R1;
         const int r1 = row - r0 * G::R1;
         const bool ok = r0 < lim0 && r1 < lim1;
+        const int e = ok ? r0 * p0e + r1 * p1e + ch * (G::PADDED ? C : G::VEC) : 0;
         if (q < PERB - 1 || sl < G::SLOTS)
-            __builtin_amdgcn_global_load_lds((global_u32x4*)(g + (ok ? r0 * p0v + r1 * p1v + ch : 0)),
+            __builtin_amdgcn_global_load_lds((global_u32x4*)(g + e),
                                              (__attribute__((address_space(3))) void*)(lds + q * B + wbase),
                                              16, 0, 0);
     }
@@ -1025,13 +1063,14 @@ constexpr int tile_lds_bytes() {
 // box of geometry G at cell origin (o0, o1, o2), evaluated by one workgroup
 // of B threads from an LDS copy of the box's block of the grid.  All 16-byte
 // loads of the block are issued at once (one memory round trip) straight into
-// `lds` (block_lds_bytes() of it).  Two lanes per particle (one half of the
-// axis-0 sum each, combined with a lane shuffle) when the box holds at most
-// B/2 particles, one lane per particle otherwise.  Every thread of the
+// `lds` (block_lds_bytes() of it); with `fill` false the LDS already holds the
+// block (the previous call was for the same box).  Two lanes per particle (one
+// half of the axis-0 sum each, combined with a lane shuffle) when there are
+// at most B/2 particles, one lane per particle otherwise.  Every thread of the
 // workgroup calls this with the same arguments.
 template <int N, typename CT, int C, bool GRAD, typename G, int B>
 __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, int o1, int o2, uint32_t count,
-                                                 uint32_t start, u32x4* lds) {
+                                                 uint32_t start, u32x4* lds, bool fill = true) {
     using AT = typename Acc<CT>::type;
     static_assert(sizeof(CT) != 2 || bf16_rows_fit<N, C, G::R2 - N + 1, G::LROW>(),
                   "BF16 row reads would leave the LDS row");
@@ -1064,7 +1103,9 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
     // memory round trip serves both (4 % faster for order 6)
     fetch_round(0);
     {
-        block_dma<N, CT, C, G, B>(static_cast<const CT*>(a.grid), a.n0, a.n1, a.P1, long(a.pitch2), o0, o1, o2, lds);
+        if (fill)
+            block_dma<N, CT, C, G, B>(static_cast<const CT*>(a.grid), a.n0, a.n1, a.P1, long(a.pitch2), o0, o1, o2,
+                                      lds);
         // the weights' arithmetic stays below every block load: the compiler
         // waits for all loads in flight before the first use of a position,
         // so arithmetic scheduled between the block loads would split them
@@ -1080,7 +1121,7 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
         // first particle and store nothing
         if (j0 + uint32_t((pair ? 32 : 64) * (tid / 64)) < count) {
             const CT* base =
-                tile + ((cell[0] - o0) * G::R1 + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * C;
+                tile + ((cell[0] - o0) * G::R1 + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * G::PS;
             auto rows = [base](int ia, int ib) { return base + (ia * G::R1 + ib) * G::LROW; };
             if (pair) {
                 // both lanes of a pair run the same instructions: lane `half`
@@ -1093,7 +1134,7 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
                     wd0s[k] = half ? wd[0][N / 2 + k] : wd[0][k];
                 }
                 Partial<AT, C> mine, other;
-                contract_planes<N, CT, AT, C, GRAD, N / 2, true>(
+                contract_planes<N, CT, AT, C, GRAD, N / 2, true, G::PS>(
                     w0s, wd0s, w, wd, [&](int k, int ib) { return rows(ia0 + k, ib); }, mine);
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
@@ -1105,8 +1146,8 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
                 if (active && half == 0) store_sum<AT, C, GRAD>(a, p, mine, other);
             } else {
                 Partial<AT, C> lo, hi;
-                contract_planes<N, CT, AT, C, GRAD, N / 2, true>(w[0], wd[0], w, wd, rows, lo);
-                contract_planes<N, CT, AT, C, GRAD, N / 2, true>(
+                contract_planes<N, CT, AT, C, GRAD, N / 2, true, G::PS>(w[0], wd[0], w, wd, rows, lo);
+                contract_planes<N, CT, AT, C, GRAD, N / 2, true, G::PS>(
                     w[0] + N / 2, wd[0] + N / 2, w, wd, [&](int k, int ib) { return rows(N / 2 + k, ib); },
                     hi);
                 if (active) store_sum<AT, C, GRAD>(a, p, lo, hi);
@@ -1128,25 +1169,89 @@ __device__ __forceinline__ void nonfinite_eval(const GatherArgs& a, uint32_t cou
     if (threadIdx.x == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
 }
 
-// All particles of Morton tile `cur` (T^3 cells) evaluated by one workgroup of
-// B threads (block_eval_cells).  `cur` == nbuckets_finite is the bucket of
-// particles without a cell.  Every thread of the workgroup must call this
-// with the same `cur`.
+// The `count` binned particles from slot `start` of bucket `cur` (Morton tile
+// `cur` of T^3 cells, or the bucket of particles without a cell when `cur` ==
+// nbuckets_finite) evaluated by one workgroup of B threads
+// (block_eval_cells); `fill` false: the LDS holds tile `cur`'s block already.
+// Every thread of the workgroup must call this with the same arguments.
 template <int N, typename CT, int C, bool GRAD, int T, int B>
-__device__ __forceinline__ void tile_eval(const GatherArgs& a, uint32_t cur, u32x4* tile_v) {
+__device__ __forceinline__ void bucket_eval(const GatherArgs& a, uint32_t cur, uint32_t count, uint32_t start,
+                                            u32x4* tile_v, bool fill = true) {
     using AT = typename Acc<CT>::type;
-    // every value that steers a loop or branch holding a barrier is made
-    // wave-uniform explicitly, so that those loops are scalar
-    const uint32_t count = __builtin_amdgcn_readfirstlane(a.hist[cur]);
-    const uint32_t start = __builtin_amdgcn_readfirstlane(a.offs[cur]);
     if (cur == a.nbuckets_finite) {
         nonfinite_eval<AT, C, GRAD, B>(a, count, start);
     } else {
         const int o0 = int(compact3(cur >> 2)) * T;
         const int o1 = int(compact3(cur >> 1)) * T;
         const int o2 = int(compact3(cur)) * T;
-        block_eval_cells<N, CT, C, GRAD, TileGeom<N, CT, C, T>, B>(a, o0, o1, o2, count, start, tile_v);
+        block_eval_cells<N, CT, C, GRAD, TileGeom<N, CT, C, T>, B>(a, o0, o1, o2, count, start, tile_v, fill);
     }
+}
+
+// All particles of bucket `cur` (bucket_eval).
+template <int N, typename CT, int C, bool GRAD, int T, int B>
+__device__ __forceinline__ void tile_eval(const GatherArgs& a, uint32_t cur, u32x4* tile_v) {
+    // every value that steers a loop or branch holding a barrier is made
+    // wave-uniform explicitly, so that those loops are scalar
+    const uint32_t count = __builtin_amdgcn_readfirstlane(a.hist[cur]);
+    const uint32_t start = __builtin_amdgcn_readfirstlane(a.offs[cur]);
+    bucket_eval<N, CT, C, GRAD, T, B>(a, cur, count, start, tile_v);
+}
+
+// ------------------------------------------------------- work items ---------
+// The tiled gather's work: every non-empty bucket cut into items of at most
+// `chunk` binned particles, so that a crowded tile is shared by several
+// workgroups.  The items are split into ITEM_RANGES contiguous ranges (one per
+// XCD: neighbouring tiles, whose blocks overlap, meet in the same L2); the
+// persistent workgroups of an XCD take the items of its range in order through
+// an atomic counter, then those of the other ranges.
+
+constexpr int ITEM_RANGES = 8;
+// ctl[0] = item count; the next item of range x at ctl[ITEM_CTL_STRIDE * (x + 1)],
+// each counter on a 128-byte line of its own (atomics on one line serialise)
+constexpr int ITEM_CTL_STRIDE = 32;
+constexpr int ITEM_CTL_WORDS = ITEM_CTL_STRIDE * (ITEM_RANGES + 1);
+// items a workgroup takes from a range with one atomic
+constexpr uint32_t ITEM_TAKE = 4;
+
+// One workgroup per SCAN_CHUNK consecutive buckets: their item counts are
+// scanned, the workgroup's items are appended at an offset reserved with one
+// atomic on ctl[0] (zero before the launch) in bucket order.  The order of the
+// workgroups' groups of items is the order of their atomics.
+static __global__ __launch_bounds__(SCAN_BLOCK) void k_items(const uint32_t* __restrict__ hist,
+                                                      const uint32_t* __restrict__ offs, long nb, uint32_t chunk,
+                                                      u32x4* __restrict__ items, uint32_t* ctl) {
+    __shared__ uint32_t sh[SCAN_BLOCK];
+    __shared__ uint32_t base;
+    const long b0 = long(blockIdx.x) * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
+    uint32_t cnt[SCAN_ITEMS], pieces[SCAN_ITEMS];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        cnt[i] = b0 + i < nb ? hist[b0 + i] : 0u;
+        pieces[i] = (cnt[i] + chunk - 1) / chunk;
+        sum += pieces[i];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, sh, &total);
+    if (threadIdx.x == 0) base = atomicAdd(ctl, total);
+    __syncthreads();
+    run += base;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (pieces[i] == 0) continue;
+        const uint32_t st = offs[b0 + i];
+        for (uint32_t k = 0; k < pieces[i]; ++k) {
+            const uint32_t first = k * chunk;
+            items[run + k] = u32x4{uint32_t(b0 + i), st + first, min(chunk, cnt[i] - first), 0u};
+        }
+        run += pieces[i];
+    }
+}
+
+// First item of range x of W items.
+__device__ __forceinline__ uint32_t item_range_begin(uint32_t W, uint32_t x) {
+    return uint32_t((uint64_t(W) * x) / ITEM_RANGES);
 }
 
 }  // namespace bsi

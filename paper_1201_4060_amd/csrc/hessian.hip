@@ -357,7 +357,7 @@ constexpr int HESS_SLICES = 4;   // workgroups sharing the rounds of one crowded
 template <int N, typename CT, int C>
 __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
     using AT = typename Acc<CT>::type;
-    using G = TileGeom<N, CT, C, 8>;
+    using G = TileGeom<N, CT, C, 8, false>;   // rows packed densely (hess_planes reads them)
     static_assert(sizeof(CT) != 2 || bf16_rows_fit<N, C, 8, G::LROW>(), "BF16 row reads would leave the LDS row");
     __shared__ u32x4 lds[G::SLOTS];
     const CT* tile = reinterpret_cast<const CT*>(lds);
@@ -436,8 +436,8 @@ bool hess_tiled_ok(int N, int C) {
     // FP64 three-component order 6 spills registers in the tiled body: direct
     if (sizeof(CT) == 8 && N == 6 && C == 3) return false;
     auto ok = [](auto g) { return decltype(g)::BYTES <= 65536 && decltype(g)::ALIGNED; };
-    if (N == 4) return C == 1 ? ok(TileGeom<4, CT, 1, 8>{}) : ok(TileGeom<4, CT, 3, 8>{});
-    return C == 1 ? ok(TileGeom<6, CT, 1, 8>{}) : ok(TileGeom<6, CT, 3, 8>{});
+    if (N == 4) return C == 1 ? ok(TileGeom<4, CT, 1, 8, false>{}) : ok(TileGeom<4, CT, 3, 8, false>{});
+    return C == 1 ? ok(TileGeom<6, CT, 1, 8, false>{}) : ok(TileGeom<6, CT, 3, 8, false>{});
 }
 
 template <typename CT>

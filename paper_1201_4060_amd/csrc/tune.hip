@@ -1,4 +1,4 @@
-// Autotuner of the evaluation knobs (binning tile, gather variant, tiles per
+// Autotuner of the evaluation knobs (binning tile, gather variant, item size, tiles per
 // workgroup) and the table the evaluation and batch planner consult.
 //
 // Entries are keyed by (order, coefficient type, ncomp, density class), the
@@ -170,7 +170,7 @@ bsi_status bsi_tune(bsi_field* f, int64_t P, uint64_t seed, const char* db_path,
         const double per_tile8 = double(P) * 512.0 / (double(f->n[0]) * f->n[1] * f->n[2]);
         for (int T : {4, 6, 8, 12, 16}) {
             if (T < tmin || !tiled_supported(f, T)) continue;
-            for (int tpg : {1, 2, 4}) {
+            for (int ir : {2, 4, 8}) {
                 for (int tb : {64, 256}) {
                     if (tb == 256 && (T != 8 || per_tile8 < 64.0)) continue;
                     bsi_eval_config c{};
@@ -178,7 +178,8 @@ bsi_status bsi_tune(bsi_field* f, int64_t P, uint64_t seed, const char* db_path,
                     c.block = 256;
                     c.xcd_remap = 1;
                     c.variant = 0;
-                    c.tiles_per_group = tpg;
+                    c.tiles_per_group = 2;
+                    c.item_rounds = ir;
                     c.tile_block = T == 8 ? tb : 0;
                     cands.push_back(c);
                 }
@@ -242,10 +243,10 @@ bsi_status bsi_tune(bsi_field* f, int64_t P, uint64_t seed, const char* db_path,
         std::fprintf(fp,
                      "{\"order\":%d,\"coef\":%d,\"ncomp\":%d,\"density_class\":%d,\"n\":[%d,%d,%d],"
                      "\"P\":%lld,\"sort_tile\":%d,\"variant\":%d,\"tiles_per_group\":%d,\"block\":%d,"
-                     "\"xcd_remap\":%d,\"tile_block\":%d,\"us\":%.3f}\n",
+                     "\"xcd_remap\":%d,\"tile_block\":%d,\"item_rounds\":%d,\"us\":%.3f}\n",
                      f->N, int(f->desc.coef), f->C, dcls, f->n[0], f->n[1], f->n[2], (long long)P,
                      best_cfg.sort_tile, best_cfg.variant, best_cfg.tiles_per_group, best_cfg.block,
-                     best_cfg.xcd_remap, best_cfg.tile_block, best_t);
+                     best_cfg.xcd_remap, best_cfg.tile_block, best_cfg.item_rounds, best_t);
         std::fclose(fp);
     }
     if (best) *best = best_cfg;
@@ -271,11 +272,14 @@ bsi_status bsi_ctx_load_tuning(bsi_ctx* ctx, const char* db_path) {
                         json_int(line, "tiles_per_group", &tpg) && json_int(line, "block", &blk) &&
                         json_int(line, "xcd_remap", &xcd);
         BSI_CHECK(ok, BSI_E_INVAL, std::string(db_path) + ":" + std::to_string(lineno) + ": malformed entry");
-        long long tb = 0;  // absent in entries that predate the field
+        long long tb = 0, ir = 0;  // absent in entries that predate the fields
         if (!json_int(line, "tile_block", &tb)) tb = 0;
+        if (!json_int(line, "item_rounds", &ir)) ir = 0;
         BSI_CHECK(tb == 0 || tb == 64 || tb == 256, BSI_E_INVAL,
                   std::string(db_path) + ":" + std::to_string(lineno) + ": tile_block out of range");
-        BSI_CHECK((N == 4 || N == 6) && coef >= 0 && coef <= 2 && (C == 1 || C == 3) && T >= 0 && T <= 1024 &&
+        BSI_CHECK(ir >= 0 && ir <= 1024, BSI_E_INVAL,
+                  std::string(db_path) + ":" + std::to_string(lineno) + ": item_rounds out of range");
+        BSI_CHECK((N == 2 || N == 4 || N == 6) && coef >= 0 && coef <= 2 && (C == 1 || C == 3) && T >= 0 && T <= 1024 &&
                       (var == 0 || var == 1) && tpg >= 0 && tpg <= 64 && blk >= 64 && blk <= 256 &&
                       blk % 64 == 0,
                   BSI_E_INVAL, std::string(db_path) + ":" + std::to_string(lineno) + ": value out of range");
@@ -286,6 +290,7 @@ bsi_status bsi_ctx_load_tuning(bsi_ctx* ctx, const char* db_path) {
         c.block = int(blk);
         c.xcd_remap = int(xcd);
         c.tile_block = int(tb);
+        c.item_rounds = int(ir);
         rows.push_back({std::make_tuple(int(N), int(coef), int(C), int(d)), c});
     }
     std::lock_guard<std::mutex> lk(ctx->mu);

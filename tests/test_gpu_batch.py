@@ -267,16 +267,16 @@ def test_tuner_roundtrip(ctx, tmp_path):
             f"tpg {best.tiles_per_group}: {us:.1f} us")
         assert us > 0
         got = bsi._bsi.bsi_ctx_lookup_config(ctx.handle, f.handle, 50000)
-        assert (got.sort_tile, got.variant, got.tiles_per_group, got.tile_block) == \
-            (best.sort_tile, best.variant, best.tiles_per_group, best.tile_block)
+        assert (got.sort_tile, got.variant, got.tiles_per_group, got.tile_block, got.item_rounds) == \
+            (best.sort_tile, best.variant, best.tiles_per_group, best.tile_block, best.item_rounds)
         text = open(db).read().strip().splitlines()
         assert len(text) == 1 and '"order":6' in text[0]
         with bsi.Context(0) as c2:
             bsi._bsi.bsi_ctx_load_tuning(c2.handle, db)
             with bsi.Field(c2, 48, 3, 6, bsi.BSI_F32) as f2:
                 got2 = bsi._bsi.bsi_ctx_lookup_config(c2.handle, f2.handle, 50000)
-                assert (got2.sort_tile, got2.variant, got2.tile_block) == \
-                    (best.sort_tile, best.variant, best.tile_block)
+                assert (got2.sort_tile, got2.variant, got2.tile_block, got2.item_rounds) == \
+                    (best.sort_tile, best.variant, best.tile_block, best.item_rounds)
         # the tuned choice gives the same bits as any other configuration
         pos = dev(synth.uniform_positions(50000, seed=9))
         u0, g0 = f.eval(pos)

@@ -84,9 +84,10 @@ def test_gather_results_independent_of_tuning(ctx):
         f.set_coefficients(dev(grid))
         ref = None
         for tile in (0, 1, 2, 4, 6, 8, 10, 12, 16, 32):
-            for block, variant, tb in ((64, 0, 0), (256, 0, 0), (128, 1, 0), (256, 0, 256)):
-                u, g = f.eval(dev(pos), cfg=bsi.EvalConfig(sort_tile=tile, block=block, xcd_remap=1,
-                                                           variant=variant, tile_block=tb))
+            for block, variant, tb, ir, remap in ((64, 0, 0, 0, 1), (256, 0, 0, 1, 0), (128, 1, 0, 0, 1),
+                                                  (256, 0, 256, 3, 1)):
+                u, g = f.eval(dev(pos), cfg=bsi.EvalConfig(sort_tile=tile, block=block, xcd_remap=remap,
+                                                           variant=variant, tile_block=tb, item_rounds=ir))
                 cur = (host(u), host(g))
                 if ref is None:
                     ref = cur
@@ -110,11 +111,12 @@ def test_gather_crowded_bucket(ctx):
     with bsi.Field(ctx, 32, 3, 6, bsi.BSI_F64) as f:
         f.set_coefficients(dev(grid))
         ref = None
-        for tile, variant, tpg in ((8, 0, 2), (4, 0, 1), (8, 1, 1), (0, 1, 1), (2, 1, 1)):
-            log(f"  crowded: tile {tile} variant {variant}")
+        # the crowded tile is cut into work items of 1 .. 16 rounds
+        for tile, variant, ir in ((8, 0, 0), (8, 0, 1), (8, 0, 16), (4, 0, 2), (8, 1, 0), (0, 1, 0), (2, 1, 0)):
+            log(f"  crowded: tile {tile} variant {variant} item rounds {ir}")
             before = f.nonfinite_count()
             u, g = f.eval(dev(pos), cfg=bsi.EvalConfig(sort_tile=tile, block=256, xcd_remap=1,
-                                                       variant=variant, tiles_per_group=tpg))
+                                                       variant=variant, item_rounds=ir))
             u, g = host(u), host(g)
             assert f.nonfinite_count() - before == 7
             if ref is None:
