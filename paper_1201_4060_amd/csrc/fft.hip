@@ -33,6 +33,8 @@ template <int LEN, bool FIRST>
 constexpr int strided_lds_kb() {
     return (FIRST && LEN >= 512) ? BSI_FFT_LDS_KB_LONG_FIRST : BSI_FFT_LDS_KB;
 }
+// LDS budget of the narrow instance (a single leftover column)
+#define BSI_FFT_LDS_KB_NARROW 8
 // XCD-contiguous block order (k_fft_axis): the first pass with two blocks per CU
 template <int LEN, bool FIRST>
 constexpr bool fft_remap() {
@@ -178,13 +180,17 @@ struct StridedCfg {
 // FIRST: input is the caller's spectrum (InT pairs), multiplied by the FP64
 // symbol cAxis[a] * cOther[other] * c2[k2]; otherwise in-place on the work
 // buffer (in == out).
-template <typename T, typename InT, int LEN, bool FIRST>
-__global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cplx<T>* out, int H, int gx, int gy,
+// Columns [k2_begin, k2_end) of the half spectrum are transformed.  NARROW:
+// an instance with few lines per workgroup, for a last column left over by
+// the wide blocks (k2 = n2/2 when n2/2 is a multiple of their width).
+template <typename T, typename InT, int LEN, bool FIRST, bool NARROW = false>
+__global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cplx<T>* out, int k2_begin,
+                                                  int k2_end, int gx, int gy,
                                                   long sAxis, long sOther, long sComp, long oAxis, long oOther,
                                                   long oComp, const double* cAxis,
                                                   const double* cOther, const double* c2,
                                                   const cplx<T>* twg, int quarter) {
-    using Cfg = StridedCfg<T, LEN, strided_lds_kb<LEN, FIRST>()>;
+    using Cfg = StridedCfg<T, LEN, NARROW ? BSI_FFT_LDS_KB_NARROW : strided_lds_kb<LEN, FIRST>()>;
     constexpr int W = Cfg::W;
     constexpr int LP = LEN + 1;
     __shared__ cplx<T> lines[W * LP];
@@ -198,7 +204,7 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
     // caller's (unaligned) rows are L2 hits.  Elsewhere the plain
     // three-dimensional grid measured as fast or faster.
     int bx, other, bz;
-    if constexpr (fft_remap<LEN, FIRST>()) {
+    if constexpr (!NARROW && fft_remap<LEN, FIRST>()) {
         const long nblocks = gridDim.x;
         const long q8 = nblocks / 8, r8 = nblocks % 8, x8 = blockIdx.x % 8;
         const long lb = x8 * q8 + (x8 < r8 ? x8 : r8) + blockIdx.x / 8;
@@ -210,7 +216,7 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
         other = blockIdx.y;
         bz = blockIdx.z;
     }
-    const int k2_0 = bx * W;
+    const int k2_0 = k2_begin + bx * W;
     const long base = long(bz) * sComp + long(other) * sOther + k2_0;
     const long obase = long(bz) * oComp + long(other) * oOther + k2_0;
 
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(BSI_FFT_THREADS) void k_fft_axis(const InT* in, cpl
     static_assert(LEN % RSTEP == 0, "line length must be a multiple of the row step");
     const int w = tid % W;
     const int a0 = tid / W;
-    const bool valid = k2_0 + w < H;
+    const bool valid = k2_0 + w < k2_end;
     const long lane_base = base + (valid ? w : 0) + long(a0) * sAxis;
     const long step = long(RSTEP) * sAxis;
     const long olane_base = obase + (valid ? w : 0) + long(a0) * oAxis;
@@ -449,16 +455,24 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
                        long sComp, long oAxis, long oOther, long oComp, const double* cAxis,
                        const double* cOther, const double* c2,
                        const cplx<T>* tw, hipStream_t s, int* Wout, int quarter = 0) {
+// A last block of wide lines holding a single column (k2 = n2/2 when n2/2 is a
+// multiple of the width) is replaced by a narrow launch for that column.
 #define BSI_AXIS_CASE(L)                                                                           \
     case L: {                                                                                      \
         using Cfg = StridedCfg<T, L, strided_lds_kb<L, FIRST>()>;                                  \
+        using CfgN = StridedCfg<T, L, BSI_FFT_LDS_KB_NARROW>;                                      \
         *Wout = Cfg::W;                                                                            \
-        const int gx = (H + Cfg::W - 1) / Cfg::W;                                                  \
+        const int full = H - 1 >= Cfg::W && (H - 1) % Cfg::W == 0 ? H - 1 : H;                    \
+        const int gx = (full + Cfg::W - 1) / Cfg::W;                                               \
         const dim3 g = fft_remap<L, FIRST>() ? dim3(unsigned(gx) * grid.y * grid.z)              \
                                               : dim3(unsigned(gx), grid.y, grid.z);              \
-        hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), g, dim3(Cfg::THREADS), 0, s, in, out, H, gx, \
+        hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST>), g, dim3(Cfg::THREADS), 0, s, in, out, 0, full, gx, \
                            int(grid.y), sAxis, sOther, sComp, oAxis, oOther, oComp, cAxis, cOther, c2, tw, \
                            quarter);                                                              \
+        if (full < H)                                                                              \
+            hipLaunchKernelGGL((k_fft_axis<T, InT, L, FIRST, true>), dim3(1u, grid.y, grid.z),     \
+                               dim3(CfgN::THREADS), 0, s, in, out, full, H, 1, int(grid.y), sAxis, sOther, \
+                               sComp, oAxis, oOther, oComp, cAxis, cOther, c2, tw, quarter);       \
         break;                                                                                     \
     }
     switch (len) {
