@@ -383,9 +383,9 @@ static int tiled_block(const bsi_field* f, int tile, const bsi_eval_config& cfg)
 
 // Work items of the tiled gather after the binning's arrays: at most one per
 // non-empty bucket plus one per `chunk` particles, 16 bytes each, then the
-// control words.
+// control words and the per-group item sums.
 struct ItemLayout {
-    size_t items, ctl, bytes;
+    size_t items, ctl, sums, bytes;
     uint32_t chunk;
 };
 
@@ -395,10 +395,12 @@ static ItemLayout item_layout(const bsi_field* f, long P, int tile, const bsi_ev
     l.items = l.ctl = l.bytes = base;
     if (B == 0) return l;
     l.chunk = uint32_t(B) * uint32_t(cfg.item_rounds > 0 ? cfg.item_rounds : 4);
-    const size_t cap = bin_bucket_count(f, tile) + 1 + size_t(P) / l.chunk + 1;
+    const size_t nb = bin_bucket_count(f, tile) + 1;
+    const size_t cap = nb + size_t(P) / l.chunk + 1;
     l.items = (base + 15) / 16 * 16;
     l.ctl = l.items + cap * 16;
-    l.bytes = l.ctl + ITEM_CTL_WORDS * sizeof(uint32_t);
+    l.sums = l.ctl + ITEM_CTL_WORDS * sizeof(uint32_t);
+    l.bytes = l.sums + (nb + SCAN_CHUNK - 1) / SCAN_CHUNK * sizeof(uint32_t);
     return l;
 }
 
@@ -478,8 +480,12 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
             StageTimer tm(f->ctx, "bin_items", s);
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ga.ctl, long(ITEM_CTL_WORDS), 0u);
             const long nb = long(nbf) + 1;
-            hipLaunchKernelGGL(k_items, dim3(unsigned((nb + SCAN_CHUNK - 1) / SCAN_CHUNK)), dim3(SCAN_BLOCK), 0, s,
-                               hist, offs, nb, il.chunk, reinterpret_cast<u32x4*>(w + il.items), ga.ctl);
+            const unsigned ng = unsigned((nb + SCAN_CHUNK - 1) / SCAN_CHUNK);
+            uint32_t* sums = reinterpret_cast<uint32_t*>(w + il.sums);
+            hipLaunchKernelGGL(k_item_sums, dim3(ng), dim3(SCAN_BLOCK), 0, s, hist, nb, il.chunk, sums);
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, sums, int(ng));
+            hipLaunchKernelGGL(k_items, dim3(ng), dim3(SCAN_BLOCK), 0, s, hist, offs, nb, il.chunk, sums,
+                               reinterpret_cast<u32x4*>(w + il.items), ga.ctl);
         }
         StageTimer tm(f->ctx, "gather", s);
         bool ok = false;

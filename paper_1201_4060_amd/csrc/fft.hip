@@ -455,14 +455,16 @@ bsi_status launch_axis(int len, dim3 grid, const InT* in, cplx<T>* out, int H, l
                        long sComp, long oAxis, long oOther, long oComp, const double* cAxis,
                        const double* cOther, const double* c2,
                        const cplx<T>* tw, hipStream_t s, int* Wout, int quarter = 0) {
-// A last block of wide lines holding a single column (k2 = n2/2 when n2/2 is a
-// multiple of the width) is replaced by a narrow launch for that column.
+// In the first pass, a last block of wide lines holding a single column (k2 =
+// n2/2 when n2/2 is a multiple of the width) is replaced by a narrow launch for
+// that column (512^3 x3 FP32: 1273 -> 1136 + 52 us; in pass B the narrow
+// launch costs what it saves).
 #define BSI_AXIS_CASE(L)                                                                           \
     case L: {                                                                                      \
         using Cfg = StridedCfg<T, L, strided_lds_kb<L, FIRST>()>;                                  \
         using CfgN = StridedCfg<T, L, BSI_FFT_LDS_KB_NARROW>;                                      \
         *Wout = Cfg::W;                                                                            \
-        const int full = H - 1 >= Cfg::W && (H - 1) % Cfg::W == 0 ? H - 1 : H;                    \
+        const int full = FIRST && H - 1 >= Cfg::W && (H - 1) % Cfg::W == 0 ? H - 1 : H;           \
         const int gx = (full + Cfg::W - 1) / Cfg::W;                                               \
         const dim3 g = fft_remap<L, FIRST>() ? dim3(unsigned(gx) * grid.y * grid.z)              \
                                               : dim3(unsigned(gx), grid.y, grid.z);              \

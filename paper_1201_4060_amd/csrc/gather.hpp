@@ -1200,8 +1200,8 @@ __device__ __forceinline__ void tile_eval(const GatherArgs& a, uint32_t cur, u32
 
 // ------------------------------------------------------- work items ---------
 // The tiled gather's work: every non-empty bucket cut into items of at most
-// `chunk` binned particles, so that a crowded tile is shared by several
-// workgroups.  The items are split into ITEM_RANGES contiguous ranges (one per
+// `chunk` binned particles (in bucket order), so that a crowded tile is shared
+// by several workgroups.  The items are split into ITEM_RANGES contiguous ranges (one per
 // XCD: neighbouring tiles, whose blocks overlap, meet in the same L2); the
 // persistent workgroups of an XCD take the items of its range in order through
 // an atomic counter, then those of the other ranges.
@@ -1214,17 +1214,9 @@ constexpr int ITEM_CTL_WORDS = ITEM_CTL_STRIDE * (ITEM_RANGES + 1);
 // items a workgroup takes from a range with one atomic
 constexpr uint32_t ITEM_TAKE = 4;
 
-// One workgroup per SCAN_CHUNK consecutive buckets: their item counts are
-// scanned, the workgroup's items are appended at an offset reserved with one
-// atomic on ctl[0] (zero before the launch) in bucket order.  The order of the
-// workgroups' groups of items is the order of their atomics.
-static __global__ __launch_bounds__(SCAN_BLOCK) void k_items(const uint32_t* __restrict__ hist,
-                                                      const uint32_t* __restrict__ offs, long nb, uint32_t chunk,
-                                                      u32x4* __restrict__ items, uint32_t* ctl) {
-    __shared__ uint32_t sh[SCAN_BLOCK];
-    __shared__ uint32_t base;
-    const long b0 = long(blockIdx.x) * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
-    uint32_t cnt[SCAN_ITEMS], pieces[SCAN_ITEMS];
+// Items of buckets [b0, b0 + SCAN_ITEMS) of thread t (per-thread counts).
+__device__ __forceinline__ uint32_t item_pieces(const uint32_t* __restrict__ hist, long nb, uint32_t chunk, long b0,
+                                                uint32_t* cnt, uint32_t* pieces) {
     uint32_t sum = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
@@ -1232,11 +1224,35 @@ static __global__ __launch_bounds__(SCAN_BLOCK) void k_items(const uint32_t* __r
         pieces[i] = (cnt[i] + chunk - 1) / chunk;
         sum += pieces[i];
     }
+    return sum;
+}
+
+// Items in bucket order, in three launches: k_item_sums (items per
+// SCAN_CHUNK buckets), k_scan_top over those sums, k_items (each workgroup
+// scans its buckets' counts from its sum's offset and writes their items; the
+// last one also writes the item count ctl[0]).
+static __global__ __launch_bounds__(SCAN_BLOCK) void k_item_sums(const uint32_t* __restrict__ hist, long nb,
+                                                          uint32_t chunk, uint32_t* __restrict__ sums) {
+    __shared__ uint32_t sh[SCAN_BLOCK];
+    uint32_t cnt[SCAN_ITEMS], pieces[SCAN_ITEMS];
+    const uint32_t s =
+        item_pieces(hist, nb, chunk, long(blockIdx.x) * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS, cnt, pieces);
     uint32_t total;
-    uint32_t run = block_exclusive_scan(sum, sh, &total);
-    if (threadIdx.x == 0) base = atomicAdd(ctl, total);
-    __syncthreads();
-    run += base;
+    block_exclusive_scan(s, sh, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+static __global__ __launch_bounds__(SCAN_BLOCK) void k_items(const uint32_t* __restrict__ hist,
+                                                      const uint32_t* __restrict__ offs, long nb, uint32_t chunk,
+                                                      const uint32_t* __restrict__ sums, u32x4* __restrict__ items,
+                                                      uint32_t* ctl) {
+    __shared__ uint32_t sh[SCAN_BLOCK];
+    const long b0 = long(blockIdx.x) * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
+    uint32_t cnt[SCAN_ITEMS], pieces[SCAN_ITEMS];
+    const uint32_t s = item_pieces(hist, nb, chunk, b0, cnt, pieces);
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, sh, &total) + sums[blockIdx.x];
+    if (blockIdx.x + 1 == gridDim.x && threadIdx.x == 0) ctl[0] = sums[blockIdx.x] + total;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
         if (pieces[i] == 0) continue;
