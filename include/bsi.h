@@ -337,13 +337,20 @@ bsi_status bsi_server_add_field(bsi_server* server, int32_t field_id, bsi_field*
 bsi_status bsi_server_submit(bsi_server* server, int32_t field_id, const double* pos_host, int64_t P,
                              void* u_host, void* grad_host, uint64_t* ticket);
 /* *done = 1 once the request has completed (its outputs are in host memory);
- * the return value is then the request's own status.  latency_ns may be NULL. */
+ * the return value is then the request's own status.  latency_ns may be NULL.
+ * A completed request's record is released once it has been collected: when
+ * bsi_server_poll reports it done or bsi_server_wait returns it; a later poll
+ * or wait of that ticket returns BSI_E_INVAL.  The server keeps the records
+ * of requests completed and not yet collected, so callers collect every
+ * ticket. */
 bsi_status bsi_server_poll(bsi_server* server, uint64_t ticket, int32_t* done, int64_t* latency_ns);
-/* Block until the request completes; returns its status. */
+/* Block until the request completes; returns its status (and collects it). */
 bsi_status bsi_server_wait(bsi_server* server, uint64_t ticket, int64_t* latency_ns);
 /* Block until every submitted request has completed. */
 bsi_status bsi_server_drain(bsi_server* server);
-/* Latency percentiles and throughput of the requests completed since the last reset. */
+/* Latency percentiles and throughput of the requests completed since the last
+ * reset (percentiles over at most 2^20 requests: a uniform sample of them
+ * when more have completed). */
 bsi_status bsi_server_stats(bsi_server* server, bsi_server_report* out);
 bsi_status bsi_server_reset_stats(bsi_server* server);
 /* Finish every submitted request, stop the scheduler and free the server. */

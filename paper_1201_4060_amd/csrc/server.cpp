@@ -20,6 +20,7 @@
 #include <map>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "common.hpp"
@@ -129,13 +130,19 @@ struct bsi_server {
     std::condition_variable cv_done;  // a request finished
     std::condition_variable cv_work;  // new request or shutdown
     std::deque<Request> waiting;
+    // tickets submitted and not finished; finished and not yet collected (a
+    // record is released when bsi_server_wait returns it or bsi_server_poll
+    // reports it done)
+    std::unordered_set<uint64_t> pending;
     std::unordered_map<uint64_t, Done> done;
     uint64_t next_ticket = 1;
     int64_t inflight = 0, queued_or_running = 0;
     bool stop = false;
-    // statistics since the last reset
+    // statistics since the last reset: latencies of at most STATS_CAP
+    // completed requests (a uniform sample of them beyond that)
     std::vector<int64_t> lat_ns, dev_ns;
-    int64_t points = 0, rejected = 0, t_first = 0, t_last = 0, max_inflight = 0;
+    int64_t completed = 0, points = 0, rejected = 0, t_first = 0, t_last = 0, max_inflight = 0;
+    uint64_t sample_state = 0x9e3779b97f4a7c15ull;
 
     std::thread worker;
 };
@@ -172,6 +179,17 @@ bsi_status launch(bsi_server* sv, Slot& sl) {
     return BSI_OK;
 }
 
+// Latency samples kept for the percentiles.
+constexpr size_t STATS_CAP = size_t(1) << 20;
+
+// SplitMix64 step (Steele, Lea and Flood 2014) for the latency sample.
+uint64_t next_sample(uint64_t& state) {
+    uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
 void finish(bsi_server* sv, const Request& r, bsi_status st, const std::string& msg, int64_t dev_ns) {
     const int64_t t = now_ns();
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -181,10 +199,22 @@ void finish(bsi_server* sv, const Request& r, bsi_status st, const std::string& 
     d.device_ns = dev_ns;
     d.msg = msg;
     sv->done[r.ticket] = d;
+    sv->pending.erase(r.ticket);
     sv->queued_or_running--;
     if (st == BSI_OK) {
-        sv->lat_ns.push_back(d.latency_ns);
-        sv->dev_ns.push_back(dev_ns);
+        // reservoir sample: request k (1-based) replaces a kept one with
+        // probability STATS_CAP / k once the sample is full
+        sv->completed++;
+        if (sv->lat_ns.size() < STATS_CAP) {
+            sv->lat_ns.push_back(d.latency_ns);
+            sv->dev_ns.push_back(dev_ns);
+        } else {
+            const uint64_t j = next_sample(sv->sample_state) % uint64_t(sv->completed);
+            if (j < STATS_CAP) {
+                sv->lat_ns[j] = d.latency_ns;
+                sv->dev_ns[j] = dev_ns;
+            }
+        }
         sv->points += r.P;
         sv->t_last = std::max(sv->t_last, t);
     } else {
@@ -366,6 +396,7 @@ bsi_status bsi_server_submit(bsi_server* sv, int32_t field_id, const double* pos
     BSI_CHECK(int64_t(sv->waiting.size()) < sv->cfg.queue_capacity, BSI_E_BUSY, "request queue is full");
     r.ticket = sv->next_ticket++;
     if (sv->t_first == 0) sv->t_first = t;
+    sv->pending.insert(r.ticket);
     sv->waiting.push_back(r);
     sv->queued_or_running++;
     *ticket = r.ticket;
@@ -380,13 +411,16 @@ bsi_status bsi_server_poll(bsi_server* sv, uint64_t ticket, int32_t* done, int64
     BSI_CHECK(ticket >= 1 && ticket < sv->next_ticket, BSI_E_INVAL, "unknown ticket");
     auto it = sv->done.find(ticket);
     if (it == sv->done.end()) {
+        BSI_CHECK(sv->pending.count(ticket) != 0, BSI_E_INVAL, "ticket already collected");
         *done = 0;
         return BSI_OK;
     }
     *done = 1;
     if (latency_ns) *latency_ns = it->second.latency_ns;
-    if (it->second.status != BSI_OK) set_error(it->second.msg);
-    return it->second.status;
+    const bsi_status st = it->second.status;
+    if (st != BSI_OK) set_error(it->second.msg);
+    sv->done.erase(it);
+    return st;
 }
 
 bsi_status bsi_server_wait(bsi_server* sv, uint64_t ticket, int64_t* latency_ns) {
@@ -394,11 +428,15 @@ bsi_status bsi_server_wait(bsi_server* sv, uint64_t ticket, int64_t* latency_ns)
     BSI_CHECK(sv != nullptr, BSI_E_INVAL, "NULL argument");
     std::unique_lock<std::mutex> lk(sv->mu);
     BSI_CHECK(ticket >= 1 && ticket < sv->next_ticket, BSI_E_INVAL, "unknown ticket");
+    BSI_CHECK(sv->done.count(ticket) != 0 || sv->pending.count(ticket) != 0, BSI_E_INVAL,
+              "ticket already collected");
     sv->cv_done.wait(lk, [&] { return sv->done.count(ticket) != 0; });
-    const Done& d = sv->done[ticket];
-    if (latency_ns) *latency_ns = d.latency_ns;
-    if (d.status != BSI_OK) set_error(d.msg);
-    return d.status;
+    auto it = sv->done.find(ticket);
+    if (latency_ns) *latency_ns = it->second.latency_ns;
+    const bsi_status st = it->second.status;
+    if (st != BSI_OK) set_error(it->second.msg);
+    sv->done.erase(it);
+    return st;
 }
 
 bsi_status bsi_server_drain(bsi_server* sv) {
@@ -414,7 +452,7 @@ bsi_status bsi_server_stats(bsi_server* sv, bsi_server_report* out) {
     BSI_CHECK(sv && out, BSI_E_INVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(sv->mu);
     *out = bsi_server_report{};
-    out->completed = int64_t(sv->lat_ns.size());
+    out->completed = sv->completed;
     out->failed = sv->rejected;
     out->p50_ns = percentile(sv->lat_ns, 0.50);
     out->p99_ns = percentile(sv->lat_ns, 0.99);
@@ -434,7 +472,7 @@ bsi_status bsi_server_reset_stats(bsi_server* sv) {
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->lat_ns.clear();
     sv->dev_ns.clear();
-    sv->points = sv->rejected = sv->t_first = sv->t_last = sv->max_inflight = 0;
+    sv->completed = sv->points = sv->rejected = sv->t_first = sv->t_last = sv->max_inflight = 0;
     return BSI_OK;
 }
 

@@ -150,6 +150,23 @@ def test_admission_by_budget_and_errors(served):
             bsi._bsi.bsi_server_submit(sv.handle, 0, p, 0, u)
         with pytest.raises(bsi.BsiError):
             sv.add_field(0, fields[0])
+        # a collected ticket's record is released: waiting or polling it again
+        # is an error; a request polled to completion is collected as well
+        assert st["completed"] == len(tickets)
+        with pytest.raises(bsi.BsiError) as e:
+            bsi._bsi.bsi_server_wait(sv.handle, tickets[0])
+        assert e.value.status == 1
+        with pytest.raises(bsi.BsiError) as e:
+            bsi._bsi.bsi_server_poll(sv.handle, tickets[-1])
+        assert e.value.status == 1
+        fid, p, u = reqs[0]
+        t = sv.submit(fid, p, u)
+        while not sv.poll(t)[0]:
+            pass
+        with pytest.raises(bsi.BsiError):
+            bsi._bsi.bsi_server_wait(sv.handle, t)
+        with pytest.raises(bsi.BsiError):   # never issued
+            bsi._bsi.bsi_server_poll(sv.handle, t + 1)
 
 
 def test_served_full_size(served):
