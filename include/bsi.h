@@ -359,7 +359,7 @@ void bsi_server_destroy(bsi_server* server);
 /* ---- autotuning ------------------------------------------------------------- */
 
 /* Time the candidate configurations of the evaluation (LDS-tiled gather with
- * sort tiles 4, 6, 8, 12, 16 and 1, 2, 4 tiles per workgroup; one lane per
+ * sort tiles 4, 6, 8, 12, 16 and work items of 2, 4, 8 rounds; one lane per
  * particle binned by 4, 8, 16, 32) on P uniform positions generated on the
  * device from `seed`, and keep the fastest in the context's table under
  * (order, coefficient type, ncomp, density class round(log2(P / n0 n1 n2))).
