@@ -117,6 +117,7 @@ typedef struct bsi_eval_config {
 typedef struct bsi_ctx bsi_ctx;
 typedef struct bsi_field bsi_field;
 typedef struct bsi_server bsi_server;
+typedef struct bsi_eval_plan bsi_eval_plan;
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -204,6 +205,32 @@ bsi_status bsi_eval_ex(bsi_field* field, const double* pos_dev, int64_t P,
 bsi_status bsi_eval_static(bsi_field* field, const double* pos_dev, int64_t P,
                            void* u_dev, void* grad_dev, const bsi_eval_config* cfg,
                            void* hip_stream);
+
+/* An evaluation in two halves (the same work and results as bsi_eval_ex, bitwise):
+ * bsi_eval_plan_bin does everything that depends on the positions only (cell,
+ * Morton binning, work items: Section 5's stencil rule), bsi_eval_plan_run the
+ * gather and contraction from that binning and the field's grid as it is when
+ * the run executes.  The binning can thus run on another stream while the
+ * field's prefilter (bsi_field_set_spectrum) runs, and one binning serves
+ * several runs (the field's grid may change in between).
+ *
+ * bsi_eval_plan_create: a plan for `field` and up to max_particles positions,
+ * with its own device workspace (allocated here, freed by destroy) and the
+ * configuration *cfg (NULL: the context's tuned one for max_particles).
+ * bsi_eval_plan_bin: bins P <= max_particles positions pos_dev [P][3] FP64 on
+ * the stream; pos_dev belongs to the caller and must stay unchanged until the
+ * last run that uses this binning has completed.  BSI_E_INVAL if P exceeds the
+ * plan's capacity.
+ * bsi_eval_plan_run: u_dev [P][ncomp], grad_dev [P][ncomp][3] or NULL, as
+ * bsi_eval; BSI_E_INVAL before the first bin.  The caller orders a run after
+ * its bin (same stream, or an event) and after the field's prefilter; calls on
+ * one plan that overlap race.
+ * A plan must be destroyed before its field. */
+bsi_status bsi_eval_plan_create(bsi_field* field, int64_t max_particles, const bsi_eval_config* cfg,
+                                bsi_eval_plan** out);
+bsi_status bsi_eval_plan_bin(bsi_eval_plan* plan, const double* pos_dev, int64_t P, void* hip_stream);
+bsi_status bsi_eval_plan_run(bsi_eval_plan* plan, void* u_dev, void* grad_dev, void* hip_stream);
+void bsi_eval_plan_destroy(bsi_eval_plan* plan);
 
 /* (B-spline fields of orders 4 and 6; BSI_E_UNSUPPORTED for other fields.)
  * u, grad u and the second derivatives at P particles (Section 2: the l-th

@@ -13,8 +13,8 @@ from . import _bsi
 from ._bsi import (BsiError, BSI_F64, BSI_F32, BSI_BF16, BSI_PREFILTER_L2OPT,
                    BSI_PREFILTER_INTERP, BSI_PREFILTER_NONE, BSI_BASIS_BSPLINE, BSI_BASIS_LAGRANGE,
                    BSI_BASIS_HERMITE, EvalConfig)
-from .api import Batch, Context, Field, Server
+from .api import Batch, Context, EvalPlan, Field, Server
 
 __all__ = ["_bsi", "BsiError", "BSI_F64", "BSI_F32", "BSI_BF16", "BSI_PREFILTER_L2OPT",
            "BSI_PREFILTER_INTERP", "BSI_PREFILTER_NONE", "BSI_BASIS_BSPLINE", "BSI_BASIS_LAGRANGE",
-           "BSI_BASIS_HERMITE", "EvalConfig", "Batch", "Context", "Field", "Server"]
+           "BSI_BASIS_HERMITE", "EvalConfig", "Batch", "Context", "EvalPlan", "Field", "Server"]

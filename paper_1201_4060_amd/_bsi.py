@@ -91,6 +91,10 @@ SIGNATURES = {
     "bsi_eval": (ST, [VP, VP, I64, VP, VP, VP]),
     "bsi_eval_ex": (ST, [VP, VP, I64, VP, VP, ctypes.POINTER(EvalConfig), VP]),
     "bsi_eval_static": (ST, [VP, VP, I64, VP, VP, ctypes.POINTER(EvalConfig), VP]),
+    "bsi_eval_plan_create": (ST, [VP, I64, ctypes.POINTER(EvalConfig), ctypes.POINTER(VP)]),
+    "bsi_eval_plan_bin": (ST, [VP, VP, I64, VP]),
+    "bsi_eval_plan_run": (ST, [VP, VP, VP, VP]),
+    "bsi_eval_plan_destroy": (None, [VP]),
     "bsi_debug_cells": (ST, [VP, VP, I64, VP, VP, VP]),
     "bsi_eval_hessian": (ST, [VP, VP, I64, VP, VP, VP, VP]),
     "bsi_debug_bins": (ST, [VP, VP, I64, I32, VP, VP, VP, VP, ctypes.POINTER(I64), VP]),
@@ -225,6 +229,25 @@ def bsi_eval_ex(field, pos, P, u, grad=None, cfg=None, stream=None):
 def bsi_eval_static(field, pos, P, u, grad=None, cfg=None, stream=None):
     c = ctypes.byref(cfg) if cfg is not None else None
     _check(lib().bsi_eval_static(field, _ptr(pos), P, _ptr(u), _ptr(grad), c, stream), "bsi_eval_static")
+
+
+def bsi_eval_plan_create(field, max_particles, cfg=None):
+    out = VP()
+    c = ctypes.byref(cfg) if cfg is not None else None
+    _check(lib().bsi_eval_plan_create(field, max_particles, c, ctypes.byref(out)), "bsi_eval_plan_create")
+    return out.value
+
+
+def bsi_eval_plan_bin(plan, pos, P, stream=None):
+    _check(lib().bsi_eval_plan_bin(plan, _ptr(pos), P, stream), "bsi_eval_plan_bin")
+
+
+def bsi_eval_plan_run(plan, u, grad=None, stream=None):
+    _check(lib().bsi_eval_plan_run(plan, _ptr(u), _ptr(grad), stream), "bsi_eval_plan_run")
+
+
+def bsi_eval_plan_destroy(plan):
+    lib().bsi_eval_plan_destroy(plan)
 
 
 def bsi_eval_hessian(field, pos, P, u, grad, hess, stream=None):

@@ -145,6 +145,47 @@ class Field:
         return _bsi.bsi_field_stats(self.handle)
 
 
+class EvalPlan:
+    """bsi_eval_plan: an evaluation of `field` split into a binning of the
+    positions (bin, on any stream) and the gather from it (run), for up to
+    `max_particles` positions.  The positions passed to bin must stay alive
+    and unchanged while runs use them."""
+
+    def __init__(self, field, max_particles, cfg=None):
+        self.field = field
+        self.handle = _bsi.bsi_eval_plan_create(field.handle, max_particles, cfg)
+        self._pos = None
+
+    def bin(self, pos):
+        assert pos.is_cuda and pos.is_contiguous() and pos.dtype == torch.float64
+        assert pos.dim() == 2 and pos.shape[1] == 3
+        _bsi.bsi_eval_plan_bin(self.handle, pos, pos.shape[0], _stream())
+        self._pos = pos
+
+    def run(self, grad=True, out=None):
+        """-> (u [P][C], grad [P][C][3] or None) at the last binned positions."""
+        assert self._pos is not None, "bin positions first"
+        P, f = self._pos.shape[0], self.field
+        if out is None:
+            u = torch.empty((P, f.ncomp), dtype=f.out_dtype, device=self._pos.device)
+            g = torch.empty((P, f.ncomp, 3), dtype=f.out_dtype, device=self._pos.device) if grad else None
+        else:
+            u, g = out
+        _bsi.bsi_eval_plan_run(self.handle, u, g, _stream())
+        return u, g
+
+    def close(self):
+        if self.handle:
+            _bsi.bsi_eval_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 class Batch:
     """bsi_batch: evaluations of several fields run by one persistent gather.
 

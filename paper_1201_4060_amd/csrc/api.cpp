@@ -417,6 +417,87 @@ bsi_status bsi_eval_ex(bsi_field* f, const double* pos, int64_t P, void* u, void
     return eval_run(f, pos, P, u, grad, c, s);
 }
 
+}  // extern "C"
+
+struct bsi_eval_plan {
+    bsi_field* f = nullptr;
+    bsi_eval_config cfg{};
+    int64_t cap = 0;
+    int64_t P = -1;              // particles of the last binning (-1: none yet)
+    const double* pos = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+extern "C" {
+
+bsi_status bsi_eval_plan_create(bsi_field* f, int64_t max_particles, const bsi_eval_config* cfg,
+                                bsi_eval_plan** out) {
+    clear_error();
+    BSI_CHECK(f && out, BSI_E_INVAL, "NULL argument");
+    *out = nullptr;
+    BSI_CHECK(max_particles >= 0 && max_particles < (int64_t(1) << 31), BSI_E_INVAL,
+              "max_particles must be in [0, 2^31)");
+    BSI_HIP(hipSetDevice(f->ctx->device));
+    bsi_eval_config c{};
+    if (cfg) c = *cfg;
+    else BSI_TRY(lookup_config(f->ctx, f, std::max<int64_t>(max_particles, 1), &c));
+    BSI_TRY(eval_check_config(c));
+    auto* pl = new bsi_eval_plan;
+    pl->f = f;
+    pl->cfg = c;
+    pl->cap = max_particles;
+    pl->ws_bytes = max_particles > 0 ? eval_ws_bytes(f, max_particles, c) : 0;
+    if (pl->ws_bytes && hipMalloc(&pl->ws, pl->ws_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete pl;
+        set_error("cannot allocate the plan's workspace");
+        return BSI_E_NOMEM;
+    }
+    *out = pl;
+    return BSI_OK;
+}
+
+bsi_status bsi_eval_plan_bin(bsi_eval_plan* pl, const double* pos, int64_t P, void* stream) {
+    clear_error();
+    BSI_CHECK(pl != nullptr, BSI_E_INVAL, "plan is NULL");
+    BSI_CHECK(P >= 0 && P <= pl->cap, BSI_E_INVAL, "P exceeds the plan's capacity");
+    if (P > 0) BSI_TRY(check_device_ptr(pos, "pos"));
+    bsi_field* f = pl->f;
+    BSI_CHECK(eval_ws_bytes(f, P, pl->cfg) <= pl->ws_bytes, BSI_E_INVAL,
+              "the binning of P particles needs more than the plan's workspace");
+    BSI_HIP(hipSetDevice(f->ctx->device));
+    hipStream_t s = pick_stream(f->ctx, stream);
+    BSI_TRY(eval_bin_ws(f, pos, P, pl->cfg, s, pl->ws));
+    pl->P = P;
+    pl->pos = pos;
+    return BSI_OK;
+}
+
+bsi_status bsi_eval_plan_run(bsi_eval_plan* pl, void* u, void* grad, void* stream) {
+    clear_error();
+    BSI_CHECK(pl != nullptr, BSI_E_INVAL, "plan is NULL");
+    BSI_CHECK(pl->P >= 0, BSI_E_INVAL, "the plan has not binned any positions");
+    if (pl->P == 0) return BSI_OK;
+    BSI_TRY(check_device_ptr(u, "u"));
+    if (grad) BSI_TRY(check_device_ptr(grad, "grad"));
+    bsi_field* f = pl->f;
+    BSI_HIP(hipSetDevice(f->ctx->device));
+    hipStream_t s = pick_stream(f->ctx, stream);
+    f->last_stream = s;
+    return eval_gather_ws(f, pl->pos, pl->P, u, grad, pl->cfg, s, pl->ws);
+}
+
+void bsi_eval_plan_destroy(bsi_eval_plan* pl) {
+    if (!pl) return;
+    if (pl->ws) {
+        (void)hipSetDevice(pl->f->ctx->device);
+        (void)hipDeviceSynchronize();   // no run may still read the workspace
+        (void)hipFree(pl->ws);
+    }
+    delete pl;
+}
+
 bsi_status bsi_eval_hessian(bsi_field* f, const double* pos, int64_t P, void* u, void* grad, void* hess,
                             void* stream) {
     clear_error();

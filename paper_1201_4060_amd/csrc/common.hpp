@@ -261,10 +261,17 @@ bsi_status grid_from_dense(bsi_field* f, const double* dense, hipStream_t s);
 bsi_status grid_to_dense(const bsi_field* f, double* dense, hipStream_t s);
 bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
                     const bsi_eval_config& cfg, hipStream_t s);
-// evaluation with a caller-provided workspace of eval_ws_bytes() bytes
+// evaluation with a caller-provided workspace of eval_ws_bytes() bytes; it is
+// eval_bin_ws (positions only: binning and work items) then eval_gather_ws
+// (the gather from that binning and the field's current grid)
 size_t eval_ws_bytes(const bsi_field* f, int64_t P, const bsi_eval_config& cfg);
+bsi_status eval_check_config(const bsi_eval_config& cfg);
 bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
                        const bsi_eval_config& cfg, hipStream_t s, void* ws);
+bsi_status eval_bin_ws(bsi_field* f, const double* pos, int64_t P, const bsi_eval_config& cfg, hipStream_t s,
+                       void* ws);
+bsi_status eval_gather_ws(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
+                          const bsi_eval_config& cfg, hipStream_t s, void* ws);
 bsi_status lookup_config(bsi_ctx* ctx, const bsi_field* f, int64_t P, bsi_eval_config* out);
 bsi_status check_device_ptr_ex(const void* p, const char* what);
 bsi_status debug_cells_run(bsi_field* f, const double* pos, int64_t P, int32_t* cell, double* t,

@@ -410,20 +410,63 @@ size_t eval_ws_bytes(const bsi_field* f, int64_t P, const bsi_eval_config& cfg) 
     return item_layout(f, P, tile, cfg, bin_layout(f, P, tile).bytes).bytes;
 }
 
-bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
-                       const bsi_eval_config& cfg, hipStream_t s, void* ws) {
-    if (P == 0) return BSI_OK;
-    int block = cfg.block > 0 ? cfg.block : 256;
+bsi_status eval_check_config(const bsi_eval_config& cfg) {
+    const int block = cfg.block > 0 ? cfg.block : 256;
     BSI_CHECK(block % 64 == 0 && block >= 64 && block <= 256, BSI_E_INVAL,
               "eval block must be 64, 128, 192 or 256");
+    BSI_CHECK(cfg.sort_tile >= 0 && cfg.sort_tile <= 1024, BSI_E_INVAL, "sort_tile out of range");
     BSI_CHECK(cfg.tile_block == 0 || cfg.tile_block == 64 || cfg.tile_block == 256, BSI_E_INVAL,
               "tile_block must be 0, 64 or 256");
     BSI_CHECK(cfg.item_rounds >= 0 && cfg.item_rounds <= 1024, BSI_E_INVAL, "item_rounds must be 0..1024");
-    const uint32_t* perm = nullptr;
-    const double* pos_sorted = nullptr;
-    const uint32_t* hist = nullptr;
-    const uint32_t* offs = nullptr;
+    return BSI_OK;
+}
+
+// The position-only half of an evaluation: binning and work items into ws
+// (nothing without binning).
+bsi_status eval_bin_ws(bsi_field* f, const double* pos, int64_t P, const bsi_eval_config& cfg, hipStream_t s,
+                       void* ws) {
     const int tile = effective_tile(f, cfg);
+    if (P == 0 || tile == 0) return BSI_OK;
+    BSI_CHECK(ws != nullptr && reinterpret_cast<uintptr_t>(ws) % 16 == 0, BSI_E_INVAL,
+              "binned evaluation needs a 16-byte aligned workspace");
+    const BinLayout l = bin_layout(f, P, tile);
+    char* w = static_cast<char*>(ws);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(w + l.hist);
+    uint32_t* offs = reinterpret_cast<uint32_t*>(w + l.offs);
+    BSI_TRY(bin_run(f, pos, P, tile, w + l.grp, reinterpret_cast<uint32_t*>(w + l.perm),
+                    reinterpret_cast<double*>(w + l.pos), hist, offs, s));
+    const ItemLayout il = item_layout(f, P, tile, cfg, l.bytes);
+    if (il.chunk > 0) {
+        StageTimer tm(f->ctx, "bin_items", s);
+        uint32_t* ctl = reinterpret_cast<uint32_t*>(w + il.ctl);
+        const long nb = long(bin_bucket_count(f, tile)) + 1;
+        const unsigned ng = unsigned((nb + SCAN_CHUNK - 1) / SCAN_CHUNK);
+        uint32_t* sums = reinterpret_cast<uint32_t*>(w + il.sums);
+        hipLaunchKernelGGL(k_item_sums, dim3(ng), dim3(SCAN_BLOCK), 0, s, hist, nb, il.chunk, sums);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, sums, int(ng));
+        hipLaunchKernelGGL(k_items, dim3(ng), dim3(SCAN_BLOCK), 0, s, hist, offs, nb, il.chunk, sums,
+                           reinterpret_cast<u32x4*>(w + il.items), ctl);
+    }
+    BSI_HIP(hipGetLastError());
+    return BSI_OK;
+}
+
+// The gather half: reads the binning eval_bin_ws left in ws for the same
+// (pos, P, cfg) and the field's current grid.
+bsi_status eval_gather_ws(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
+                          const bsi_eval_config& cfg, hipStream_t s, void* ws) {
+    if (P == 0) return BSI_OK;
+    const int block = cfg.block > 0 ? cfg.block : 256;
+    const int tile = effective_tile(f, cfg);
+    GatherArgs ga;
+    ga.grid = f->grid;
+    ga.pos = pos;
+    ga.perm = nullptr;
+    ga.pos_sorted = nullptr;
+    ga.hist = nullptr;
+    ga.offs = nullptr;
+    ga.items = nullptr;
+    ga.ctl = nullptr;
     size_t nbf = 0;
     ItemLayout il{};
     if (tile > 0) {
@@ -431,25 +474,17 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
                   "binned evaluation needs a 16-byte aligned workspace");
         const BinLayout l = bin_layout(f, P, tile);
         char* w = static_cast<char*>(ws);
-        double* ps = reinterpret_cast<double*>(w + l.pos);
-        uint32_t* pm = reinterpret_cast<uint32_t*>(w + l.perm);
-        uint32_t* hs = reinterpret_cast<uint32_t*>(w + l.hist);
-        uint32_t* os = reinterpret_cast<uint32_t*>(w + l.offs);
-        BSI_TRY(bin_run(f, pos, P, tile, w + l.grp, pm, ps, hs, os, s));
-        perm = pm;
-        pos_sorted = ps;
-        hist = hs;
-        offs = os;
+        ga.pos_sorted = reinterpret_cast<const double*>(w + l.pos);
+        ga.perm = reinterpret_cast<const uint32_t*>(w + l.perm);
+        ga.hist = reinterpret_cast<const uint32_t*>(w + l.hist);
+        ga.offs = reinterpret_cast<const uint32_t*>(w + l.offs);
         nbf = bin_bucket_count(f, tile);
         il = item_layout(f, P, tile, cfg, l.bytes);
+        if (il.chunk > 0) {
+            ga.items = reinterpret_cast<const u32x4*>(w + il.items);
+            ga.ctl = reinterpret_cast<uint32_t*>(w + il.ctl);
+        }
     }
-    GatherArgs ga;
-    ga.grid = f->grid;
-    ga.pos = pos;
-    ga.perm = perm;
-    ga.pos_sorted = pos_sorted;
-    ga.hist = hist;
-    ga.offs = offs;
     ga.u = u;
     ga.grad = grad;
     ga.nonfinite = f->counters;
@@ -464,30 +499,19 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
     ga.ih0 = f->inv_h[0];
     ga.ih1 = f->inv_h[1];
     ga.ih2 = f->inv_h[2];
-    ga.xcd_remap = (perm && cfg.xcd_remap) ? 1 : 0;
+    ga.xcd_remap = (ga.perm && cfg.xcd_remap) ? 1 : 0;
     ga.nbuckets_finite = uint32_t(nbf);
     ga.basis = f->basis;
     ga.cs = f->cs;
-    ga.items = nullptr;
-    ga.ctl = nullptr;
     const bool g = grad != nullptr;
-    const bool tiled = perm && il.chunk > 0;
-    if (tiled) {
-        char* w = static_cast<char*>(ws);
-        ga.items = reinterpret_cast<const u32x4*>(w + il.items);
-        ga.ctl = reinterpret_cast<uint32_t*>(w + il.ctl);
-        {
-            StageTimer tm(f->ctx, "bin_items", s);
-            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ga.ctl, long(ITEM_CTL_WORDS), 0u);
-            const long nb = long(nbf) + 1;
-            const unsigned ng = unsigned((nb + SCAN_CHUNK - 1) / SCAN_CHUNK);
-            uint32_t* sums = reinterpret_cast<uint32_t*>(w + il.sums);
-            hipLaunchKernelGGL(k_item_sums, dim3(ng), dim3(SCAN_BLOCK), 0, s, hist, nb, il.chunk, sums);
-            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, sums, int(ng));
-            hipLaunchKernelGGL(k_items, dim3(ng), dim3(SCAN_BLOCK), 0, s, hist, offs, nb, il.chunk, sums,
-                               reinterpret_cast<u32x4*>(w + il.items), ga.ctl);
-        }
-        StageTimer tm(f->ctx, "gather", s);
+    if (ga.items) {
+        // the ranges' counters start at zero for every run over one binning
+        StageTimer tm(f->ctx, "bin_items", s);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ga.ctl + ITEM_CTL_STRIDE,
+                           long(ITEM_CTL_WORDS - ITEM_CTL_STRIDE), 0u);
+    }
+    StageTimer tm(f->ctx, "gather", s);
+    if (ga.items) {
         bool ok = false;
         // tile_block 256 asks for four wavefronts per 8^3 tile (dense tiles)
         const bool wide = cfg.tile_block == 256;
@@ -497,7 +521,6 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
         else ok = launch_tiled_ct<uint16_t>(f->N, f->C, tile, ga, g, wide, ncu, s);
         BSI_CHECK(ok, BSI_E_UNSUPPORTED, "no tiled gather instance for this tile size");
     } else {
-        StageTimer tm(f->ctx, "gather", s);
         const unsigned nb = unsigned((P + block - 1) / block);
         if (f->desc.coef == BSI_F64) launch_gather_ct<double>(f->N, f->C, ga, g, nb, block, s);
         else if (f->desc.coef == BSI_F32) launch_gather_ct<float>(f->N, f->C, ga, g, nb, block, s);
@@ -505,6 +528,14 @@ bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void
     }
     BSI_HIP(hipGetLastError());
     return BSI_OK;
+}
+
+bsi_status eval_run_ws(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
+                       const bsi_eval_config& cfg, hipStream_t s, void* ws) {
+    if (P == 0) return BSI_OK;
+    BSI_TRY(eval_check_config(cfg));
+    BSI_TRY(eval_bin_ws(f, pos, P, cfg, s, ws));
+    return eval_gather_ws(f, pos, P, u, grad, cfg, s, ws);
 }
 
 bsi_status eval_run(bsi_field* f, const double* pos, int64_t P, void* u, void* grad,
