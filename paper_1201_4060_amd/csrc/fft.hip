@@ -407,6 +407,104 @@ __global__ __launch_bounds__(256) void k_c2r(const cplx<T>* __restrict__ work, i
     }
 }
 
+// Pass C of a Hermite field pair: from one line X of the half spectrum (the
+// axis-0/1 derivative factors already applied) the fields with axis-2
+// derivative order 0 and 1 -- Y[k] = i d[k] X[k], d the derivative table of
+// axis 2 -- each by the even/odd twist and a length-M FFT, written together:
+// doubled grid entry 2 g + a2 (+ the offsets a0, a1 of axes 0 and 1) holds
+// field a2 at grid point g, so whole rows are written.  dtab[k] = 2 pi k / n2
+// for k < M, 0 at the Nyquist index M.
+template <typename T, typename OutT, int M, int C>
+__global__ __launch_bounds__(256) void k_c2r_dual(const cplx<T>* __restrict__ work, int Hp,
+                                                  OutT* __restrict__ grid, int n0, int n1, int P0, int P1, int P2,
+                                                  int pitch2, const cplx<T>* __restrict__ twg,
+                                                  const double* __restrict__ dtab, int a0, int a1) {
+    using Cfg = C2rCfg<T, M, 2 * C>;
+    constexpr int H = M + 1;
+    constexpr int LP = M + 2;
+    constexpr int NL = Cfg::LINES * C;  // lines of X per block; the Y lines follow
+    __shared__ cplx<T> zb[2 * NL * LP];
+    __shared__ cplx<T> tw[2 * M];
+    const int tid = threadIdx.x;
+    const long nlines = long(n0) * n1;
+    const long line0 = long(blockIdx.x) * Cfg::LINES;
+    const long compStride = nlines * Hp;
+
+    for (int i = tid; i < 2 * M; i += Cfg::THREADS) tw[i] = twg[i];
+    constexpr int ITER = (NL * H + Cfg::THREADS - 1) / Cfg::THREADS;
+    {
+        cplx<T> v[ITER];
+#pragma unroll
+        for (int q = 0; q < ITER; ++q) {
+            const int idx = q * Cfg::THREADS + tid;
+            const int f = idx / H, k = idx - (idx / H) * H;
+            const int l = f / C, c = f - (f / C) * C;
+            const bool ok = idx < NL * H && line0 + l < nlines;
+            v[q] = work[ok ? long(c) * compStride + (line0 + l) * Hp + k : 0];
+        }
+#pragma unroll
+        for (int q = 0; q < ITER; ++q) {
+            const int idx = q * Cfg::THREADS + tid;
+            if (idx < NL * H) {
+                const int f = idx / H, k = idx - (idx / H) * H;
+                const T d = T(dtab[k]);
+                zb[f * LP + k] = v[q];
+                zb[(NL + f) * LP + k] = {-d * v[q].y, d * v[q].x};  // i d X
+            }
+        }
+    }
+    __syncthreads();
+    // even/odd twist of every line (as k_c2r)
+    for (int idx = tid; idx < 2 * NL * (M / 2 + 1); idx += Cfg::THREADS) {
+        const int f = idx / (M / 2 + 1), k = idx % (M / 2 + 1);
+        cplx<T>* X = zb + f * LP;
+        if (k == 0) {
+            const T a = X[0].x, b = X[M].x;
+            X[0] = {a + b, a - b};
+        } else {
+            const int kk = M - k;
+            const cplx<T> A = X[k], B = X[kk];
+            const cplx<T> Bc = {B.x, -B.y}, Ac = {A.x, -A.y};
+            const cplx<T> z1 = cadd(cadd(A, Bc), cmul_i(cmul(tw[k], csub(A, Bc))));
+            if (k < kk) {
+                const cplx<T> z2 = cadd(cadd(B, Ac), cmul_i(cmul(tw[kk], csub(B, Ac))));
+                X[kk] = z2;
+            }
+            X[k] = z1;
+        }
+    }
+    __syncthreads();
+    fft_stages<T, M, Cfg::TEAM, 1, 2>(zb + (tid / Cfg::TEAM) * LP, tw, tid % Cfg::TEAM);
+    // rows of the doubled grid: st = 2 with offsets (a0, a1); both parities of
+    // axis 2; one periodic ghost copy per axis where it falls inside [0, P)
+    const int rowElems = P2 * C;
+    for (int l = 0; l < Cfg::LINES; ++l) {
+        const long line = line0 + l;
+        if (line >= nlines) break;
+        const int g0 = int(line / n1), g1 = int(line % n1);
+        const int p0a = 2 * g0 + a0;
+        const int p0b = (p0a + 2 * n0 < P0) ? p0a + 2 * n0 : -1;
+        const int p1a = 2 * g1 + a1;
+        const int p1b = (p1a + 2 * n1 < P1) ? p1a + 2 * n1 : -1;
+        OutT* r_aa = grid + (long(p0a) * P1 + p1a) * pitch2;
+        OutT* r_ab = p1b >= 0 ? grid + (long(p0a) * P1 + p1b) * pitch2 : nullptr;
+        OutT* r_ba = p0b >= 0 ? grid + (long(p0b) * P1 + p1a) * pitch2 : nullptr;
+        OutT* r_bb = (p0b >= 0 && p1b >= 0) ? grid + (long(p0b) * P1 + p1b) * pitch2 : nullptr;
+        for (int e = tid; e < rowElems; e += Cfg::THREADS) {
+            const int p2 = e / C, c = e % C;
+            const int a2 = p2 & 1;
+            int g2 = p2 >> 1;
+            if (g2 >= 2 * M) g2 -= 2 * M;
+            const cplx<T> z = zb[((a2 ? NL : 0) + l * C + c) * LP + (g2 >> 1)];
+            const OutT v = store_cast<OutT>((g2 & 1) ? z.y : z.x);
+            r_aa[e] = v;
+            if (r_ab) r_ab[e] = v;
+            if (r_ba) r_ba[e] = v;
+            if (r_bb) r_bb[e] = v;
+        }
+    }
+}
+
 // Dense FP64 [C][n0][n1][n2] <-> padded interleaved grid.
 template <typename O>
 __global__ void k_from_dense(const double* __restrict__ dense, O* __restrict__ grid, int C, int n0,
@@ -540,10 +638,49 @@ bsi_status launch_c2r(int M, const cplx<T>* work, int Hp, OutT* grid, int n0, in
     return BSI_OK;
 }
 
+template <typename T, typename OutT, int C>
+bsi_status launch_c2r_dual(int M, const cplx<T>* work, int Hp, OutT* grid, int n0, int n1, int P0, int P1,
+                           int P2, int pitch2, const cplx<T>* tw, const double* dtab, int a0, int a1,
+                           hipStream_t s) {
+    const long nlines = long(n0) * n1;
+#define BSI_C2RD_CASE(MM)                                                                          \
+    case MM: {                                                                                     \
+        using Cfg = C2rCfg<T, MM, 2 * C>;                                                          \
+        const unsigned nb = unsigned((nlines + Cfg::LINES - 1) / Cfg::LINES);                      \
+        hipLaunchKernelGGL((k_c2r_dual<T, OutT, MM, C>), dim3(nb), dim3(Cfg::THREADS), 0, s, work, Hp, grid, \
+                           n0, n1, P0, P1, P2, pitch2, tw, dtab, a0, a1);                          \
+        break;                                                                                     \
+    }
+    switch (M) {
+        BSI_C2RD_CASE(4)
+        BSI_C2RD_CASE(6)
+        BSI_C2RD_CASE(8)
+        BSI_C2RD_CASE(12)
+        BSI_C2RD_CASE(16)
+        BSI_C2RD_CASE(24)
+        BSI_C2RD_CASE(32)
+        BSI_C2RD_CASE(48)
+        BSI_C2RD_CASE(64)
+        BSI_C2RD_CASE(96)
+        BSI_C2RD_CASE(128)
+        BSI_C2RD_CASE(192)
+        BSI_C2RD_CASE(256)
+        BSI_C2RD_CASE(384)
+        BSI_C2RD_CASE(512)
+        default:
+            set_error("unsupported real FFT length " + std::to_string(2 * M));
+            return BSI_E_UNSUPPORTED;
+    }
+#undef BSI_C2RD_CASE
+    BSI_HIP(hipGetLastError());
+    return BSI_OK;
+}
+
 template <typename T, typename InT, typename OutT>
 bsi_status prefilter_pass(bsi_field* f, const InT* uhat, OutT* grid, cplx<T>* work, int H, int Hp, long sComp,
                           long wComp, const double* const* ct, const int* a, int st, int quarter,
-                          const void* tw0, const void* tw1, const void* tw2, hipStream_t s);
+                          const void* tw0, const void* tw1, const void* tw2, hipStream_t s,
+                          const double* dual_tab = nullptr);
 
 template <typename T, typename InT, typename OutT>
 bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_t s) {
@@ -566,27 +703,41 @@ bsi_status prefilter_typed(bsi_field* f, const InT* uhat, OutT* grid, hipStream_
     const long sComp = long(n0) * n1 * H;    // caller's spectrum
     const long wComp = long(n0) * n1 * Hp;   // work buffer
     // one inverse FFT per stored field: the prefiltered (or plain) field, or
-    // for Hermite the 8 derivative fields d^(a0+a1+a2) u / ds0^a0 ds1^a1 ds2^a2
+    // for Hermite the 8 derivative fields d^(a0+a1+a2) u / ds0^a0 ds1^a1 ds2^a2,
+    // where the two fields of each (a0, a1) share the axis-0 and axis-1 passes
+    // and one pass C writes both (k_c2r_dual)
     const bool herm = f->basis == BSI_BASIS_HERMITE;
-    for (int fld = 0; fld < (herm ? 8 : 1); ++fld) {
-        const int a[3] = {(fld >> 2) & 1, (fld >> 1) & 1, fld & 1};
+    const int nn[3] = {n0, n1, n2};
+    if (!herm) {
+        const int a[3] = {0, 0, 0};
         const double* ct[3];
-        const int nn[3] = {n0, n1, n2};
-        for (int d = 0; d < 3; ++d)
-            BSI_TRY(get_ctable(ctx, nn[d], f->N, herm ? (a[d] ? DERIVATIVE_TABLE : BSI_PREFILTER_NONE)
-                                                      : f->desc.prefilter, &ct[d]));
-        BSI_TRY((prefilter_pass<T, InT, OutT>(f, uhat, grid, work, H, Hp, sComp, wComp, ct, a, herm ? 2 : 1,
-                                              (a[0] + a[1] + a[2]) & 3, tw0, tw1, tw2, s)));
+        for (int d = 0; d < 3; ++d) BSI_TRY(get_ctable(ctx, nn[d], f->N, f->desc.prefilter, &ct[d]));
+        return prefilter_pass<T, InT, OutT>(f, uhat, grid, work, H, Hp, sComp, wComp, ct, a, 1, 0, tw0, tw1, tw2,
+                                            s);
+    }
+    const double* dtab2 = nullptr;
+    BSI_TRY(get_ctable(ctx, n2, f->N, DERIVATIVE_TABLE, &dtab2));
+    for (int pr = 0; pr < 4; ++pr) {
+        const int a[3] = {(pr >> 1) & 1, pr & 1, 0};
+        const double* ct[3];
+        for (int d = 0; d < 2; ++d)
+            BSI_TRY(get_ctable(ctx, nn[d], f->N, a[d] ? DERIVATIVE_TABLE : BSI_PREFILTER_NONE, &ct[d]));
+        BSI_TRY(get_ctable(ctx, n2, f->N, BSI_PREFILTER_NONE, &ct[2]));
+        BSI_TRY((prefilter_pass<T, InT, OutT>(f, uhat, grid, work, H, Hp, sComp, wComp, ct, a, 2,
+                                              (a[0] + a[1]) & 3, tw0, tw1, tw2, s, dtab2)));
     }
     return BSI_OK;
 }
 
 // The three passes of one inverse FFT: symbol tables ct[d] per axis, the
-// product times i^quarter, written at stride st with offsets a[] (see k_c2r).
+// product times i^quarter, written at stride st with offsets a[] (see k_c2r);
+// with dual_tab, pass C writes the Hermite pair of axis-2 orders 0 and 1
+// (k_c2r_dual, dual_tab the axis-2 derivative table).
 template <typename T, typename InT, typename OutT>
 bsi_status prefilter_pass(bsi_field* f, const InT* uhat, OutT* grid, cplx<T>* work, int H, int Hp, long sComp,
                           long wComp, const double* const* ct, const int* a, int st, int quarter,
-                          const void* tw0, const void* tw1, const void* tw2, hipStream_t s) {
+                          const void* tw0, const void* tw1, const void* tw2, hipStream_t s,
+                          const double* dual_tab) {
     bsi_ctx* ctx = f->ctx;
     const int n0 = f->n[0], n1 = f->n[1], n2 = f->n[2], C = f->C;
     const double *c0 = ct[0], *c1 = ct[1], *c2 = ct[2];
@@ -608,6 +759,14 @@ bsi_status prefilter_pass(bsi_field* f, const InT* uhat, OutT* grid, cplx<T>* wo
     // pass C: c2r along axis 2
     const int M = n2 / 2;
     StageTimer tm(ctx, "fft_c2r", s);
+    if (dual_tab) {
+        const cplx<T>* t2 = static_cast<const cplx<T>*>(tw2);
+        if (C == 1)
+            return launch_c2r_dual<T, OutT, 1>(M, work, Hp, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, t2,
+                                               dual_tab, a[0], a[1], s);
+        return launch_c2r_dual<T, OutT, 3>(M, work, Hp, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, t2,
+                                           dual_tab, a[0], a[1], s);
+    }
     if (C == 1)
         return launch_c2r<T, OutT, 1>(M, work, Hp, grid, n0, n1, f->P[0], f->P[1], f->P[2], f->pitch2, f->padlo,
                                       static_cast<const cplx<T>*>(tw2), s, st, a[0], a[1], a[2]);
