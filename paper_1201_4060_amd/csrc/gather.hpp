@@ -804,6 +804,108 @@ struct LdsRow<N, uint16_t, C, C> {
     }
 };
 
+// The axis-1/axis-2 sums of one axis-0 plane: v = sum_ib w1[ib] (sum_e w2[e] row[e]),
+// with v1 (w1') and v2 (w2') for the gradient.
+template <typename AT, int C>
+struct PlaneSum {
+    AT v[C], v1[C], v2[C];
+};
+
+// PlaneSum of NP consecutive planes from LDS rows row(k, ib), the rows
+// software-pipelined as in contract_planes (the same arithmetic, row by row).
+template <int N, typename CT, typename AT, int C, bool GRAD, int NP, int PS, typename RowFn>
+__device__ __forceinline__ void plane_sums(const AT (*w)[N], const AT (*wd)[N], RowFn row, PlaneSum<AT, C>* V) {
+    LdsRow<N, CT, C, PS> buf[2];
+    buf[0].load(row(0, 0));
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        AT v[C], v1[C], v2[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = v1[c] = v2[c] = AT(0);
+#pragma unroll
+        for (int ib = 0; ib < N; ++ib) {
+            const int r = k * N + ib;
+            if (r + 1 < NP * N) buf[(r + 1) & 1].load(row((r + 1) / N, (r + 1) % N));
+            const LdsRow<N, CT, C, PS>& cur = buf[r & 1];
+            AT tr[C], trd[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) tr[c] = trd[c] = AT(0);
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const AT val = widen<CT, AT>(cur.get(e * C + c));
+                    tr[c] += w[2][e] * val;
+                    if constexpr (GRAD) trd[c] += wd[2][e] * val;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                v[c] += w[1][ib] * tr[c];
+                if constexpr (GRAD) {
+                    v1[c] += wd[1][ib] * tr[c];
+                    v2[c] += w[1][ib] * trd[c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if constexpr (GRAD) asm volatile("" : "+v"(v[c]), "+v"(v1[c]), "+v"(v2[c]));
+                else asm volatile("" : "+v"(v[c]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            V[k].v[c] = v[c];
+            V[k].v1[c] = v1[c];
+            V[k].v2[c] = v2[c];
+        }
+    }
+}
+
+// out += plane k's terms (the accumulation step of contract_planes).
+template <typename AT, int C, bool GRAD>
+__device__ __forceinline__ void chain_add(Partial<AT, C>& out, AT w0k, AT wd0k, const PlaneSum<AT, C>& V) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        out.u[c] += w0k * V.v[c];
+        if constexpr (GRAD) {
+            out.g0[c] += wd0k * V.v[c];
+            out.g1[c] += w0k * V.v1[c];
+            out.g2[c] += w0k * V.v2[c];
+        }
+    }
+}
+
+template <typename AT, int C, bool GRAD>
+__device__ __forceinline__ PlaneSum<AT, C> shfl_planesum(const PlaneSum<AT, C>& V, int src) {
+    PlaneSum<AT, C> r;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        r.v[c] = __shfl(V.v[c], src, 64);
+        if constexpr (GRAD) {
+            r.v1[c] = __shfl(V.v1[c], src, 64);
+            r.v2[c] = __shfl(V.v2[c], src, 64);
+        }
+    }
+    return r;
+}
+
+template <typename AT, int C, bool GRAD>
+__device__ __forceinline__ Partial<AT, C> shfl_partial(const Partial<AT, C>& P, int src) {
+    Partial<AT, C> r;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        r.u[c] = __shfl(P.u[c], src, 64);
+        if constexpr (GRAD) {
+            r.g0[c] = __shfl(P.g0[c], src, 64);
+            r.g1[c] = __shfl(P.g1[c], src, 64);
+            r.g2[c] = __shfl(P.g2[c], src, 64);
+        }
+    }
+    return r;
+}
+
 // NIA consecutive axis-0 planes: w0[k], wd0[k] are the axis-0 weights of
 // plane k and row(k, ib) its rows; accumulation order is k = 0..NIA-1.
 // FENCE (LDS-resident rows): the NIA*N rows are software-pipelined -- the
@@ -912,6 +1014,13 @@ __device__ __forceinline__ void contract_and_store(const GatherArgs& a, long p, 
 template <typename CT, int C>
 constexpr bool padded_points() {
     return sizeof(CT) == 4 && C == 3;
+}
+
+// Lanes per particle for sparse boxes (0: none): order 6 -> three lanes of
+// two axis-0 planes each, order 4 -> four lanes of one plane each.
+template <int N>
+constexpr int split_lanes() {
+    return N == 6 ? 3 : (N == 4 ? 4 : 0);
 }
 
 // LDS copy of the (T0+N-1) x (T1+N-1) x (T2+N-1) block of grid points that
@@ -1064,10 +1173,13 @@ constexpr int tile_lds_bytes() {
 // of B threads from an LDS copy of the box's block of the grid.  All 16-byte
 // loads of the block are issued at once (one memory round trip) straight into
 // `lds` (block_lds_bytes() of it); with `fill` false the LDS already holds the
-// block (the previous call was for the same box).  Two lanes per particle (one
-// half of the axis-0 sum each, combined with a lane shuffle) when there are
-// at most B/2 particles, one lane per particle otherwise.  Every thread of the
-// workgroup calls this with the same arguments.
+// block (the previous call was for the same box).  Lanes per particle: three
+// (order 6; four for order 4) when a round holds all the particles, each lane
+// summing its axis-0 planes and the lanes of planes 0 and N/2 gathering the
+// rest of their half by lane shuffles; else two (one half of the axis-0 sum
+// each) up to B/2 particles; else one.  Every mode adds the same terms in the
+// same order.  Every thread of the workgroup calls this with the same
+// arguments.
 template <int N, typename CT, int C, bool GRAD, typename G, int B>
 __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, int o1, int o2, uint32_t count,
                                                  uint32_t start, u32x4* lds, bool fill = true) {
@@ -1076,10 +1188,20 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
                   "BF16 row reads would leave the LDS row");
     const CT* tile = reinterpret_cast<const CT*>(lds);
     const int tid = threadIdx.x;
-    const bool pair = count <= uint32_t(B / 2);
-    const int stride = pair ? B / 2 : B;
-    const uint32_t jlane = pair ? uint32_t(tid >> 1) : uint32_t(tid);
-    const int half = pair ? (tid & 1) : 0;
+    const int lane = tid & 63;
+    // a sparse box is split: SL lanes per particle (split_lanes), else two
+    // lanes per particle up to half a workgroup of particles, else one
+    constexpr int SL = split_lanes<N>();
+    constexpr int SPW = SL > 0 ? 64 / SL : 1;  // particles per wavefront when split
+    const bool split = SL > 0 && count <= uint32_t(SPW * (B / 64));
+    const bool pair = !split && count <= uint32_t(B / 2);
+    const int ppw = split ? SPW : (pair ? 32 : 64);  // particles per wavefront and round
+    const int stride = ppw * (B / 64);
+    const uint32_t jlane = split ? uint32_t((tid >> 6) * SPW + lane / (SL > 0 ? SL : 1))
+                                 : (pair ? uint32_t(tid >> 1) : uint32_t(tid));
+    const int part = split ? lane % (SL > 0 ? SL : 1) : (pair ? (tid & 1) : 0);
+    const int half = part;
+    const bool lane_ok = !split || lane < SPW * SL;  // the spare lane of a split wavefront
     if (count == 0) return;  // uniform: no barrier is skipped by part of the workgroup
     // per-lane particle state of one round: slot, position, stencil origin
     // in the block and the weights
@@ -1090,7 +1212,7 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
     AT w[3][N], wd[3][N];
     auto fetch_round = [&](uint32_t j0) {
         const uint32_t j = j0 + jlane;
-        active = j < count;
+        active = j < count && lane_ok;
         const uint32_t jj = start + (active ? j : 0u);
         p = long(a.perm[jj]);
         x[0] = a.pos_sorted[3 * long(jj)];
@@ -1119,11 +1241,52 @@ __device__ __forceinline__ void block_eval_cells(const GatherArgs& a, int o0, in
         // a wavefront without any particle in this round skips it (uniform);
         // inside a working wavefront, lanes past the end evaluate the box's
         // first particle and store nothing
-        if (j0 + uint32_t((pair ? 32 : 64) * (tid / 64)) < count) {
+        if (j0 + uint32_t(ppw * (tid / 64)) < count) {
             const CT* base =
                 tile + ((cell[0] - o0) * G::R1 + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * G::PS;
             auto rows = [base](int ia, int ib) { return base + (ia * G::R1 + ib) * G::LROW; };
-            if (pair) {
+            bool done = false;
+            if constexpr (SL > 0) {
+                if (split) {
+                    // lane `part` takes planes part*PPL .. part*PPL + PPL - 1; the
+                    // lanes holding planes 0 and N/2 gather the other planes of
+                    // their half and add them up in the order of contract_planes
+                    constexpr int PPL = N / SL;
+                    PlaneSum<AT, C> V[PPL];
+                    plane_sums<N, CT, AT, C, GRAD, PPL, G::PS>(
+                        w, wd, [&](int k, int ib) { return rows(part * PPL + k, ib); }, V);
+                    Partial<AT, C> lo, hi;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        lo.u[c] = lo.g0[c] = lo.g1[c] = lo.g2[c] = AT(0);
+                        hi.u[c] = hi.g0[c] = hi.g1[c] = hi.g2[c] = AT(0);
+                    }
+                    if constexpr (N == 6) {
+                        // part 0: planes 0, 1 (+ 2 from part 1); part 2: (3 from part 1 +) 4, 5
+                        const PlaneSum<AT, C> X = shfl_planesum<AT, C, GRAD>(V[0], (lane + 1) & 63);
+                        const PlaneSum<AT, C> Y = shfl_planesum<AT, C, GRAD>(V[1], (lane + 63) & 63);
+                        chain_add<AT, C, GRAD>(lo, w[0][0], wd[0][0], V[0]);
+                        chain_add<AT, C, GRAD>(lo, w[0][1], wd[0][1], V[1]);
+                        chain_add<AT, C, GRAD>(lo, w[0][2], wd[0][2], X);
+                        chain_add<AT, C, GRAD>(hi, w[0][3], wd[0][3], Y);
+                        chain_add<AT, C, GRAD>(hi, w[0][4], wd[0][4], V[0]);
+                        chain_add<AT, C, GRAD>(hi, w[0][5], wd[0][5], V[1]);
+                    } else {
+                        // part 0: plane 0 (+ 1 from part 1); part 2: plane 2 (+ 3 from part 3)
+                        static_assert(N == 4, "split lanes for orders 4 and 6");
+                        const PlaneSum<AT, C> X = shfl_planesum<AT, C, GRAD>(V[0], (lane + 1) & 63);
+                        chain_add<AT, C, GRAD>(lo, w[0][0], wd[0][0], V[0]);
+                        chain_add<AT, C, GRAD>(lo, w[0][1], wd[0][1], X);
+                        chain_add<AT, C, GRAD>(hi, w[0][2], wd[0][2], V[0]);
+                        chain_add<AT, C, GRAD>(hi, w[0][3], wd[0][3], X);
+                    }
+                    const Partial<AT, C> H = shfl_partial<AT, C, GRAD>(hi, (lane + 2) & 63);
+                    if (active && part == 0) store_sum<AT, C, GRAD>(a, p, lo, H);
+                    done = true;
+                }
+            }
+            if (done) {
+            } else if (pair) {
                 // both lanes of a pair run the same instructions: lane `half`
                 // takes planes half*N/2 .. half*N/2 + N/2 - 1
                 const int ia0 = half * (N / 2);
