@@ -15,11 +15,14 @@
 //   grouping    cell and Morton bucket of every particle (all items at once),
 //               grouped by bucket without global atomics (gather.hpp): bucket
 //               table, binned permutation and binned copy of the positions
-//   compact     list of the non-empty buckets of the tiled items
-//   gather      persistent: a grid of resident one-wavefront workgroups
-//               strides over the units of work -- the non-empty tiles of the
-//               tiled items, then groups of 64 consecutive binned particles of
-//               the direct items.
+//   compact     list of the non-empty buckets of the tiled items, one list
+//               per (order, components) class
+//   gather      per class present: a persistent grid of resident one-wavefront
+//               workgroups striding over the class's non-empty tiles, and a
+//               plain grid with one wavefront per group of 64 consecutive
+//               binned particles of the class's direct items.  One kernel per
+//               class and path keeps each kernel's registers and LDS to what
+//               its own bodies need.
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -30,19 +33,25 @@ namespace bsi {
 
 namespace {
 
-constexpr int BATCH_B = 64;        // threads per workgroup of the persistent gather
+constexpr int BATCH_B = 64;        // threads per workgroup of the persistent tile gather
+constexpr int UNIT = 64;           // particles per direct unit (one wavefront)
+constexpr int DIRECT_B = 256;      // threads per workgroup of the direct gather
 constexpr int BLK = 256;           // threads per workgroup of the binning kernels
+constexpr int NCLASS = 4;          // (order, components) classes: (4,1) (4,3) (6,1) (6,3)
+
+constexpr int class_of(int N, int C) { return (N == 6 ? 2 : 0) + (C == 3 ? 1 : 0); }
 enum : int32_t { MODE_DIRECT = 0, MODE_TILE8 = 2 };
 
 struct BatchItem {
     GatherArgs ga;       // hist/offs at the item's buckets; perm/pos_sorted are the batch-wide arrays
     int32_t N, C, mode, tile;
+    int32_t cls;         // class_of(N, C)
     uint32_t pbase;      // first particle slot of the item in the batch
     uint32_t bbase;      // first bucket of the item in the batch
     uint32_t nb;         // buckets of the item, the non-finite bucket included
     uint32_t pblk;       // first binning workgroup of the item
     uint32_t bblk;       // first compaction workgroup of the item (tiled items)
-    uint32_t ubase;      // first direct unit of the item (direct items)
+    uint32_t ubase;      // first direct unit of the item (direct items; units are grouped by class)
     uint32_t cbase;      // first coarse grouping range of the item
     int32_t cshift;      // item bucket b lies in coarse range cbase + (b >> cshift)
 };
@@ -57,9 +66,9 @@ struct BatchArgs {
     uint32_t* perm;
     double* pos_sorted;
     const uint32_t* cstart;       // first bucket of every coarse grouping range (+ end)
-    uint2* tile_list;             // (item, bucket) of every non-empty tile
-    uint32_t* ctr;                // [1] number of tile units ([0] unused)
-    uint32_t ndirect;
+    uint2* tile_list;             // (item, bucket) of every non-empty tile, class by class
+    uint32_t* ctr;                // [1 + class] non-empty tiles of the class ([0] unused)
+    uint32_t lbase[NCLASS];       // first tile-list slot of each class
 };
 
 // cell -> item-local Morton bucket, or the item's non-finite bucket
@@ -128,7 +137,8 @@ __global__ __launch_bounds__(BLK) void k_batch_compact(BatchArgs b) {
     const BatchItem& it = b.items[item];
     const uint32_t k = (blockIdx.x - it.bblk) * BLK + threadIdx.x;
     if (k >= it.nb) return;
-    if (b.hist[it.bbase + k] != 0u) b.tile_list[atomicAdd(&b.ctr[1], 1u)] = make_uint2(item, k);
+    if (b.hist[it.bbase + k] != 0u)
+        b.tile_list[b.lbase[it.cls] + atomicAdd(&b.ctr[1 + it.cls], 1u)] = make_uint2(item, k);
 }
 
 template <int N, typename CT, int C, int T>
@@ -137,49 +147,61 @@ constexpr bool batch_tile_ok() {
            TileGeom<N, CT, C, T>::SLOTS < 3072;
 }
 
-template <int N, typename CT, int C, bool GRAD>
-__device__ __forceinline__ void batch_tile(const GatherArgs& a, uint32_t bucket, u32x4* lds) {
-    // one tile shape (8^3 cells) per class keeps the kernel's register budget down
-    if constexpr (batch_tile_ok<N, CT, C, 8>()) tile_eval<N, CT, C, GRAD, 8, BATCH_B>(a, bucket, lds);
-}
-
-// Workgroup g takes units g, g + G, g + 2G, ... (G = grid size): the unit
-// index is the same in every lane, so the loop and the class dispatch are
-// scalar and every wavefront of the workgroup meets the same barriers.
-template <typename CT, bool GRAD>
-__global__ __launch_bounds__(BATCH_B) void k_batch_gather(BatchArgs b) {
-    extern __shared__ u32x4 lds[];
-    const uint32_t ntile = __builtin_amdgcn_readfirstlane(b.ctr[1]);
-    const uint32_t total = ntile + b.ndirect;
-    for (uint32_t u = blockIdx.x; u < total; u += gridDim.x) {
-        if (u < ntile) {
-            const uint2 e = b.tile_list[u];
+// Tiles of class (N, C): workgroup g takes the class's tiles g, g + G, g + 2G,
+// ... (G = grid size); the tile index is the same in every lane, so the loop
+// is scalar and every wavefront of the workgroup meets the same barriers.
+template <typename CT, bool GRAD, int N, int C>
+__global__ __launch_bounds__(BATCH_B) void k_batch_tiles(BatchArgs b) {
+    if constexpr (batch_tile_ok<N, CT, C, 8>()) {
+        extern __shared__ u32x4 lds[];
+        constexpr int cls = class_of(N, C);
+        const uint32_t ntile = __builtin_amdgcn_readfirstlane(b.ctr[1 + cls]);
+        const uint2* list = b.tile_list + b.lbase[cls];
+        for (uint32_t u = blockIdx.x; u < ntile; u += gridDim.x) {
+            const uint2 e = list[u];
             const uint32_t item = __builtin_amdgcn_readfirstlane(e.x);
             const uint32_t bucket = __builtin_amdgcn_readfirstlane(e.y);
-            const BatchItem& it = b.items[item];
-            const int key = __builtin_amdgcn_readfirstlane(it.N * 2 + (it.C == 3 ? 1 : 0));
-            switch (key) {
-                case 8: batch_tile<4, CT, 1, GRAD>(it.ga, bucket, lds); break;
-                case 9: batch_tile<4, CT, 3, GRAD>(it.ga, bucket, lds); break;
-                case 12: batch_tile<6, CT, 1, GRAD>(it.ga, bucket, lds); break;
-                default: batch_tile<6, CT, 3, GRAD>(it.ga, bucket, lds); break;
-            }
-        } else {
-            const uint32_t d = u - ntile;
-            const uint32_t item = __builtin_amdgcn_readfirstlane(uint32_t(b.dunit_item[d]));
-            const BatchItem& it = b.items[item];
-            const int key = __builtin_amdgcn_readfirstlane(it.N * 2 + (it.C == 3 ? 1 : 0));
-            const long r = long(d - it.ubase) * BATCH_B + threadIdx.x;
-            const long P = it.ga.P;
-            const long j = long(it.pbase) + (r < P ? r : P - 1);  // lanes past the end repeat the last
-            switch (key) {
-                case 8: direct_eval<4, CT, 1, GRAD>(it.ga, j, r < P); break;
-                case 9: direct_eval<4, CT, 3, GRAD>(it.ga, j, r < P); break;
-                case 12: direct_eval<6, CT, 1, GRAD>(it.ga, j, r < P); break;
-                default: direct_eval<6, CT, 3, GRAD>(it.ga, j, r < P); break;
-            }
+            tile_eval<N, CT, C, GRAD, 8, BATCH_B>(b.items[item].ga, bucket, lds);
         }
     }
+}
+
+// Direct units [d0, d1) of class (N, C), one wavefront each: lane l of unit d
+// takes binned particle (d - ubase) * UNIT + l of the unit's item.  The
+// kernel has no barrier, so lanes without a particle leave at once.
+template <typename CT, bool GRAD, int N, int C>
+__global__ __launch_bounds__(DIRECT_B) void k_batch_direct(BatchArgs b, uint32_t d0, uint32_t d1) {
+    const uint32_t d = d0 + blockIdx.x * (DIRECT_B / UNIT) + threadIdx.x / UNIT;
+    if (d >= d1) return;
+    const uint32_t item = __builtin_amdgcn_readfirstlane(uint32_t(b.dunit_item[d]));
+    const BatchItem& it = b.items[item];
+    const long r = long(d - it.ubase) * UNIT + (threadIdx.x % UNIT);
+    if (r >= it.ga.P) return;
+    direct_eval<N, CT, C, GRAD>(it.ga, long(it.pbase) + r);
+}
+
+// f(CT{}, GRAD, N, C) with the launch's types as compile-time constants.
+template <typename F>
+void with_class(int coef, bool grad, int cls, F&& f) {
+    auto by_class = [&](auto ct, auto g) {
+        using I1 = std::integral_constant<int, 1>;
+        using I3 = std::integral_constant<int, 3>;
+        using I4 = std::integral_constant<int, 4>;
+        using I6 = std::integral_constant<int, 6>;
+        switch (cls) {
+            case 0: f(ct, g, I4{}, I1{}); break;
+            case 1: f(ct, g, I4{}, I3{}); break;
+            case 2: f(ct, g, I6{}, I1{}); break;
+            default: f(ct, g, I6{}, I3{}); break;
+        }
+    };
+    auto by_grad = [&](auto ct) {
+        if (grad) by_class(ct, std::true_type{});
+        else by_class(ct, std::false_type{});
+    };
+    if (coef == BSI_F64) by_grad(double{});
+    else if (coef == BSI_F32) by_grad(float{});
+    else by_grad(uint16_t{});
 }
 
 template <typename CT>
@@ -224,30 +246,6 @@ int batch_tile_lds(int coef, int N, int C, int T) {
     return tile_lds_ct<uint16_t>(N, C, T);
 }
 
-const void* gather_kernel(int coef, bool grad) {
-    if (coef == BSI_F64)
-        return grad ? reinterpret_cast<const void*>(&k_batch_gather<double, true>)
-                    : reinterpret_cast<const void*>(&k_batch_gather<double, false>);
-    if (coef == BSI_F32)
-        return grad ? reinterpret_cast<const void*>(&k_batch_gather<float, true>)
-                    : reinterpret_cast<const void*>(&k_batch_gather<float, false>);
-    return grad ? reinterpret_cast<const void*>(&k_batch_gather<uint16_t, true>)
-                : reinterpret_cast<const void*>(&k_batch_gather<uint16_t, false>);
-}
-
-void launch_gather(int coef, bool grad, unsigned grid, size_t lds, hipStream_t s, const BatchArgs& a) {
-    if (coef == BSI_F64) {
-        if (grad) hipLaunchKernelGGL((k_batch_gather<double, true>), dim3(grid), dim3(BATCH_B), lds, s, a);
-        else hipLaunchKernelGGL((k_batch_gather<double, false>), dim3(grid), dim3(BATCH_B), lds, s, a);
-    } else if (coef == BSI_F32) {
-        if (grad) hipLaunchKernelGGL((k_batch_gather<float, true>), dim3(grid), dim3(BATCH_B), lds, s, a);
-        else hipLaunchKernelGGL((k_batch_gather<float, false>), dim3(grid), dim3(BATCH_B), lds, s, a);
-    } else {
-        if (grad) hipLaunchKernelGGL((k_batch_gather<uint16_t, true>), dim3(grid), dim3(BATCH_B), lds, s, a);
-        else hipLaunchKernelGGL((k_batch_gather<uint16_t, false>), dim3(grid), dim3(BATCH_B), lds, s, a);
-    }
-}
-
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
@@ -264,13 +262,15 @@ struct bsi_batch {
     int nitems = 0;                      // items with P > 0
     uint64_t Ptot = 0, Btot = 0;
     uint32_t npblocks = 0, nbblocks = 0, ndirect = 0;
+    uint32_t dbeg[NCLASS] = {}, dend[NCLASS] = {};  // direct units of each class
+    uint32_t tbound[NCLASS] = {};   // buckets of the class's tiled items (bound on its tiles)
+    unsigned tgrid[NCLASS] = {};    // persistent tile grid of each class
+    size_t tlds[NCLASS] = {};       // LDS of the class's tile workgroups
     GrpPlan grp;                         // grouping of the particle slots by bucket
     GrpBuffers gbuf{};
     void* ws = nullptr;
     size_t ws_bytes = 0;
     BatchArgs args{};
-    unsigned grid = 0;
-    size_t lds = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -300,7 +300,7 @@ static bsi_status enqueue(bsi_batch* b, hipStream_t s) {
     bsi_ctx* ctx = b->ctx;
     if (b->nitems == 0) return BSI_OK;
     const BatchArgs& a = b->args;
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, a.ctr, 2L, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, a.ctr, long(1 + NCLASS), 0u);
     {
         StageTimer tm(ctx, "batch_bin", s);
         const BatchSlots slots{a.items, a.pblock_item};
@@ -311,7 +311,19 @@ static bsi_status enqueue(bsi_batch* b, hipStream_t s) {
     }
     {
         StageTimer tm(ctx, "batch_gather", s);
-        launch_gather(b->coef, b->grad, b->grid, b->lds, s, a);
+        for (int cls = 0; cls < NCLASS; ++cls) {
+            const unsigned tg = b->tgrid[cls];
+            const size_t tl = b->tlds[cls];
+            const uint32_t d0 = b->dbeg[cls], d1 = b->dend[cls];
+            const unsigned dg = unsigned((d1 - d0 + DIRECT_B / UNIT - 1) / (DIRECT_B / UNIT));
+            with_class(b->coef, b->grad, cls, [&](auto ct, auto g, auto n, auto c) {
+                using CT = decltype(ct);
+                constexpr bool G = decltype(g)::value;
+                constexpr int N = decltype(n)::value, C = decltype(c)::value;
+                if (tg) hipLaunchKernelGGL((k_batch_tiles<CT, G, N, C>), dim3(tg), dim3(BATCH_B), tl, s, a);
+                if (dg) hipLaunchKernelGGL((k_batch_direct<CT, G, N, C>), dim3(dg), dim3(DIRECT_B), 0, s, a, d0, d1);
+            });
+        }
     }
     BSI_HIP(hipGetLastError());
     return BSI_OK;
@@ -372,9 +384,8 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     b->grad = grad;
     b->cfgs.resize(count);
     std::vector<BatchItem> hi;
-    std::vector<uint16_t> pblock, bblock, dunit;
+    std::vector<uint16_t> pblock, bblock, dunit_cls[NCLASS];
     uint64_t Btot = 0, pbase = 0;
-    int lds = 0;
     for (int i = 0; i < count; ++i) {
         const bsi_eval_item& it = items[i];
         bsi_field* f = it.field;
@@ -415,6 +426,7 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
         g.nbuckets_finite = uint32_t(nbf);
         x.N = f->N;
         x.C = f->C;
+        x.cls = class_of(f->N, f->C);
         x.mode = mode;
         x.tile = tile;
         x.pbase = uint32_t(pbase);
@@ -424,12 +436,14 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
         const uint16_t id = uint16_t(hi.size());
         pblock.insert(pblock.end(), size_t((it.P + BLK - 1) / BLK), id);
         if (mode == MODE_DIRECT) {
-            x.ubase = uint32_t(dunit.size());
-            dunit.insert(dunit.end(), size_t((it.P + BATCH_B - 1) / BATCH_B), id);
+            std::vector<uint16_t>& du = dunit_cls[x.cls];
+            x.ubase = uint32_t(du.size());  // class-local until the classes are laid end to end
+            du.insert(du.end(), size_t((it.P + UNIT - 1) / UNIT), id);
         } else {
             x.bblk = uint32_t(bblock.size());
             bblock.insert(bblock.end(), size_t((x.nb + BLK - 1) / BLK), id);
-            lds = std::max(lds, batch_tile_lds(coef, f->N, f->C, tile));
+            b->tbound[x.cls] += x.nb;
+            b->tlds[x.cls] = size_t(batch_tile_lds(coef, f->N, f->C, tile));
         }
         hi.push_back(x);
         pbase += uint64_t(it.P);
@@ -452,6 +466,23 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
             return BSI_E_INVAL;
         }
     }
+    // direct units class by class, tile-list slots class by class
+    std::vector<uint16_t> dunit;
+    for (int c = 0; c < NCLASS; ++c) {
+        b->dbeg[c] = uint32_t(dunit.size());
+        dunit.insert(dunit.end(), dunit_cls[c].begin(), dunit_cls[c].end());
+        b->dend[c] = uint32_t(dunit.size());
+    }
+    for (auto& x : hi)
+        if (x.mode == MODE_DIRECT) x.ubase += b->dbeg[x.cls];
+    uint32_t lbase[NCLASS];
+    {
+        uint64_t l = 0;
+        for (int c = 0; c < NCLASS; ++c) {
+            lbase[c] = uint32_t(l);
+            l += b->tbound[c];
+        }
+    }
     uint32_t fine_max = 1;
     for (const auto& x : hi) {
         for (uint64_t lo = 0; lo < x.nb; lo += uint64_t(1) << x.cshift) cstart.push_back(uint32_t(x.bbase + lo));
@@ -471,7 +502,6 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     b->npblocks = uint32_t(pblock.size());
     b->nbblocks = uint32_t(bblock.size());
     b->ndirect = uint32_t(dunit.size());
-    b->lds = size_t(lds);
     if (b->nitems == 0) {
         *out = b;
         return BSI_OK;
@@ -495,7 +525,7 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     const size_t o_perm = take(pbase * sizeof(uint32_t));
     const size_t o_pos = take(3 * pbase * sizeof(double));
     const size_t o_list = take(std::max<uint64_t>(Btot, 1) * sizeof(uint2));
-    const size_t o_ctr = take(2 * sizeof(uint32_t));
+    const size_t o_ctr = take((1 + NCLASS) * sizeof(uint32_t));
     b->ws_bytes = off;
     if (hipMalloc(&b->ws, off) != hipSuccess) {
         (void)hipGetLastError();
@@ -517,7 +547,7 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     a.pos_sorted = reinterpret_cast<double*>(base + o_pos);
     a.tile_list = reinterpret_cast<uint2*>(base + o_list);
     a.ctr = reinterpret_cast<uint32_t*>(base + o_ctr);
-    a.ndirect = b->ndirect;
+    for (int c = 0; c < NCLASS; ++c) a.lbase[c] = lbase[c];
     for (auto& x : hi) {
         x.ga.hist = a.hist + x.bbase;
         x.ga.offs = a.offs + x.bbase;
@@ -537,15 +567,25 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     up(o_bblock, bblock.data(), bblock.size() * sizeof(uint16_t));
     up(o_dunit, dunit.data(), dunit.size() * sizeof(uint16_t));
     up(o_cstart, cstart.data(), cstart.size() * sizeof(uint32_t));
-    // persistent grid: as many one-wavefront workgroups as stay resident
-    int per_cu = 0;
-    if (st == BSI_OK && hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &per_cu, gather_kernel(coef, grad), BATCH_B, b->lds) != hipSuccess) {
-        (void)hipGetLastError();
-        per_cu = 0;
+    // persistent tile grids: as many one-wavefront workgroups as stay
+    // resident, at most one per bucket of the class's tiled items
+    for (int c = 0; c < NCLASS && st == BSI_OK; ++c) {
+        if (b->tbound[c] == 0) continue;
+        int per_cu = 0;
+        with_class(coef, grad, c, [&](auto ct, auto g, auto n, auto cc) {
+            using CT = decltype(ct);
+            constexpr bool G = decltype(g)::value;
+            constexpr int N = decltype(n)::value, C = decltype(cc)::value;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, reinterpret_cast<const void*>(&k_batch_tiles<CT, G, N, C>), BATCH_B, b->tlds[c]) !=
+                hipSuccess) {
+                (void)hipGetLastError();
+                per_cu = 0;
+            }
+        });
+        per_cu = std::max(1, std::min(per_cu, 32));
+        b->tgrid[c] = unsigned(std::min<uint64_t>(uint64_t(per_cu) * ctx->num_cus, b->tbound[c]));
     }
-    per_cu = std::max(1, std::min(per_cu, 32));
-    b->grid = unsigned(per_cu * ctx->num_cus);
     if (st != BSI_OK) {
         (void)hipFree(b->ws);
         delete b;

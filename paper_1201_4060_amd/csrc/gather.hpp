@@ -1113,23 +1113,18 @@ __device__ __forceinline__ void block_dma(const CT* grid, int n0, int n1, int P1
 // One particle evaluated straight from the grid in global memory (the caches
 // provide the reuse between neighbouring binned particles).  j is the
 // particle's slot in binned order, or its index when the particles are not
-// binned; positions come from the binned copy when there is one.  With store
-// false the lane computes but writes nothing (a lane past the end of a group).
+// binned; positions come from the binned copy when there is one.
 template <int N, typename CT, int C, bool GRAD>
-__device__ __forceinline__ void direct_eval(const GatherArgs& a, long j, bool store = true) {
+__device__ __forceinline__ void direct_eval(const GatherArgs& a, long j) {
     using AT = typename Acc<CT>::type;
     const long p = a.perm ? long(a.perm[j]) : j;
     const double* xp = a.pos_sorted ? a.pos_sorted + 3 * j : a.pos + 3 * p;
     const double x[3] = {xp[0], xp[1], xp[2]};
     int cell[3];
     AT w[3][N], wd[3][N];
-    // if/else rather than an early return: the function is inlined into loops
-    // that hold workgroup barriers
     if (!particle_setup_x<N, AT>(a, x, cell, w, wd)) {
-        if (store) {
-            write_nan<AT, C, GRAD>(a, p);
-            atomicAdd(a.nonfinite, 1ull);
-        }
+        write_nan<AT, C, GRAD>(a, p);
+        atomicAdd(a.nonfinite, 1ull);
     } else {
         const CT* base = static_cast<const CT*>(a.grid) + (long(a.cs * cell[0]) * a.P1 + a.cs * cell[1]) * a.pitch2 +
                          long(a.cs * cell[2]) * C;
@@ -1140,7 +1135,7 @@ __device__ __forceinline__ void direct_eval(const GatherArgs& a, long j, bool st
         contract_planes<N, CT, AT, C, GRAD, N / 2>(w[0], wd[0], w, wd, row, lo);
         contract_planes<N, CT, AT, C, GRAD, N / 2>(w[0] + N / 2, wd[0] + N / 2, w, wd,
                                                    [&](int k, int ib) { return row(N / 2 + k, ib); }, hi);
-        if (store) store_sum<AT, C, GRAD>(a, p, lo, hi);
+        store_sum<AT, C, GRAD>(a, p, lo, hi);
     }
 }
 

@@ -349,10 +349,14 @@ constexpr int HESS_SLICES = 4;   // workgroups sharing the rounds of one crowded
 // Morton tiles of 8^3 cells.  A tile's particles are evaluated in rounds of
 // one wavefront; slice s of the tile group takes rounds s, s + HESS_SLICES, ...
 // so that a crowded tile (a dense cluster of particles) is spread over several
-// CUs, and a slice without a round of a tile skips that tile.  Each working
-// slice copies the tile's (8+N-1)^3 block of the grid into LDS by the load
-// unit's DMA path; then every particle reads its stencil from LDS, two lanes
-// per particle (one half of the axis-0 sum each, combined with a lane shuffle)
+// CUs, and a slice without a round of a tile skips that tile.  The slice is
+// the grid's outer index (workgroup s * groups + group): the slice-0
+// workgroups, which do all the work of sparse tiles, are then dealt
+// round-robin over every XCD like a plain grid (with the slice as the inner
+// index they would all land on two of the eight XCDs).  Each working slice
+// copies the tile's (8+N-1)^3 block of the grid into LDS by the load unit's
+// DMA path; then every particle reads its stencil from LDS, two lanes per
+// particle (one half of the axis-0 sum each, combined with a lane shuffle)
 // when the tile holds at most 32 particles.
 template <int N, typename CT, int C>
 __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
@@ -362,8 +366,9 @@ __global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
     __shared__ u32x4 lds[G::SLOTS];
     const CT* tile = reinterpret_cast<const CT*>(lds);
     const int tid = threadIdx.x;
-    const uint32_t slice = blockIdx.x % uint32_t(HESS_SLICES);
-    const uint32_t b0 = (blockIdx.x / uint32_t(HESS_SLICES)) * uint32_t(HESS_TPG);
+    const uint32_t groups = gridDim.x / uint32_t(HESS_SLICES);
+    const uint32_t slice = blockIdx.x / groups;
+    const uint32_t b0 = (blockIdx.x % groups) * uint32_t(HESS_TPG);
     const uint32_t b1 = min(b0 + uint32_t(HESS_TPG), a.nbf + 1);
     for (uint32_t cur = b0; cur < b1; ++cur) {
         // wave-uniform values steer every loop that holds a barrier
