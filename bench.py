@@ -460,7 +460,7 @@ def form_hessian(args):
     STEP_PERCENTILES.update(pct)
     stages = {}
     for o in ORDERS:
-        stages.update(read_stages(bsi, ctxs[o], f"N{o}", names=STAGES + ("gather_hess",)))
+        stages.update(read_stages(bsi, ctxs[o], f"N{o}", names=STAGES + ("hess_items", "gather_hess")))
         bsi._bsi.bsi_ctx_set_timing(ctxs[o].handle, False)
     eprint(f"{sps * 1e3:.3f} ms/step on {args.streams} stream(s), {sps_inst * 1e3:.3f} on one stream "
            f"with stage events")

@@ -66,28 +66,6 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
     direct_eval<N, CT, C, GRAD>(a, j);
 }
 
-// Index of the next ITEM_TAKE items of range x, requested by the workgroup's
-// first lane (the value is valid in that lane only; item_take_finish makes it
-// uniform).
-__device__ __forceinline__ uint32_t item_take_issue(const GatherArgs& a, uint32_t x) {
-    uint32_t v = 0;
-    if (threadIdx.x == 0) v = atomicAdd(a.ctl + ITEM_CTL_STRIDE * (x + 1), ITEM_TAKE);
-    return v;
-}
-
-template <int B>
-__device__ __forceinline__ uint32_t item_take_finish(uint32_t v, uint32_t* sh) {
-    if constexpr (B == 64) {
-        return __builtin_amdgcn_readfirstlane(v);
-    } else {
-        if (threadIdx.x == 0) *sh = v;
-        __syncthreads();
-        const uint32_t r = __builtin_amdgcn_readfirstlane(*sh);
-        __syncthreads();
-        return r;
-    }
-}
-
 // LDS-tiled variant: persistent workgroups of B threads evaluate work items
 // (pieces of Morton tiles of T^3 cells, k_items).  A workgroup takes the items
 // of its home range in order, ITEM_TAKE at a time through the range's
@@ -112,7 +90,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
         const uint32_t x = (home + r) % ITEM_RANGES;
         const uint32_t lo = item_range_begin(W, x);
         const uint32_t hi = item_range_begin(W, x + 1);
-        uint32_t i = item_take_finish<B>(item_take_issue(a, x), &taken);
+        uint32_t i = item_take_finish<B>(item_take_issue(a.ctl, x), &taken);
         while (lo + i < hi) {
             const uint32_t m = min(ITEM_TAKE, hi - lo - i);
             uint32_t next = 0;
@@ -121,7 +99,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
                 const uint32_t cur = __builtin_amdgcn_readfirstlane(it.x);
                 const uint32_t start = __builtin_amdgcn_readfirstlane(it.y);
                 const uint32_t count = __builtin_amdgcn_readfirstlane(it.z);
-                if (k + 1 == m) next = item_take_issue(a, x);
+                if (k + 1 == m) next = item_take_issue(a.ctl, x);
                 bucket_eval<N, CT, C, GRAD, T, B>(a, cur, count, start, tile_v, cur != prev);
                 prev = cur;
             }

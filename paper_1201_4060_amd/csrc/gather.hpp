@@ -1428,4 +1428,26 @@ __device__ __forceinline__ uint32_t item_range_begin(uint32_t W, uint32_t x) {
     return uint32_t((uint64_t(W) * x) / ITEM_RANGES);
 }
 
+// Index of the next ITEM_TAKE items of range x, requested by the workgroup's
+// first lane (the value is valid in that lane only; item_take_finish makes it
+// uniform).
+__device__ __forceinline__ uint32_t item_take_issue(uint32_t* ctl, uint32_t x) {
+    uint32_t v = 0;
+    if (threadIdx.x == 0) v = atomicAdd(ctl + ITEM_CTL_STRIDE * (x + 1), ITEM_TAKE);
+    return v;
+}
+
+template <int B>
+__device__ __forceinline__ uint32_t item_take_finish(uint32_t v, uint32_t* sh) {
+    if constexpr (B == 64) {
+        return __builtin_amdgcn_readfirstlane(v);
+    } else {
+        if (threadIdx.x == 0) *sh = v;
+        __syncthreads();
+        const uint32_t r = __builtin_amdgcn_readfirstlane(*sh);
+        __syncthreads();
+        return r;
+    }
+}
+
 }  // namespace bsi

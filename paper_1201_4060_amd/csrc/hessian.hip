@@ -65,6 +65,8 @@ struct HessArgs {
     void* grad;  // or nullptr
     void* hess;
     unsigned long long* nonfinite;
+    const u32x4* items;        // work items (bucket, first slot, count) in bucket order (tiled kernel)
+    uint32_t* ctl;             // item count and per-range counters (tiled kernel)
 };
 
 // One lane per binned slot j; results are written at the particle's index.
@@ -341,98 +343,115 @@ __device__ __forceinline__ void hess_nan(const HessArgs& a, long p) {
     }
 }
 
-constexpr int HESS_TB = 64;      // threads per workgroup of the tiled kernel
-constexpr int HESS_TPG = 2;      // Morton tiles walked per workgroup
-constexpr int HESS_SLICES = 4;   // workgroups sharing the rounds of one crowded tile
+constexpr int HESS_TB = 64;           // threads per workgroup of the tiled kernel
+constexpr uint32_t HESS_ROUNDS = 4;   // rounds of one wavefront per work item
 
-// LDS-tiled variant: HESS_SLICES one-wave workgroups per HESS_TPG consecutive
-// Morton tiles of 8^3 cells.  A tile's particles are evaluated in rounds of
-// one wavefront; slice s of the tile group takes rounds s, s + HESS_SLICES, ...
-// so that a crowded tile (a dense cluster of particles) is spread over several
-// CUs, and a slice without a round of a tile skips that tile.  The slice is
-// the grid's outer index (workgroup s * groups + group): the slice-0
-// workgroups, which do all the work of sparse tiles, are then dealt
-// round-robin over every XCD like a plain grid (with the slice as the inner
-// index they would all land on two of the eight XCDs).  Each working slice
-// copies the tile's (8+N-1)^3 block of the grid into LDS by the load unit's
-// DMA path; then every particle reads its stencil from LDS, two lanes per
-// particle (one half of the axis-0 sum each, combined with a lane shuffle)
-// when the tile holds at most 32 particles.
-template <int N, typename CT, int C>
-__global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
+// The `count` binned particles from slot `start` of Morton tile `cur` (8^3
+// cells), or of the bucket without a cell when `cur` == nbf, by one
+// wavefront.  With `fill` the tile's (8+N-1)^3 block of the grid is first
+// copied into LDS by the load unit's DMA path (else the LDS holds it from the
+// previous call); then every particle reads its stencil from LDS, two lanes
+// per particle (one half of the axis-0 sum each, combined with a lane
+// shuffle) when the piece holds at most 32 particles.
+template <int N, typename CT, int C, typename G>
+__device__ __forceinline__ void hess_piece(const HessArgs& a, uint32_t cur, uint32_t start, uint32_t count,
+                                           u32x4* lds, bool fill) {
     using AT = typename Acc<CT>::type;
-    using G = TileGeom<N, CT, C, 8, false>;   // rows packed densely (hess_planes reads them)
-    static_assert(sizeof(CT) != 2 || bf16_rows_fit<N, C, 8, G::LROW>(), "BF16 row reads would leave the LDS row");
-    __shared__ u32x4 lds[G::SLOTS];
     const CT* tile = reinterpret_cast<const CT*>(lds);
     const int tid = threadIdx.x;
-    const uint32_t groups = gridDim.x / uint32_t(HESS_SLICES);
-    const uint32_t slice = blockIdx.x / groups;
-    const uint32_t b0 = (blockIdx.x % groups) * uint32_t(HESS_TPG);
-    const uint32_t b1 = min(b0 + uint32_t(HESS_TPG), a.nbf + 1);
-    for (uint32_t cur = b0; cur < b1; ++cur) {
-        // wave-uniform values steer every loop that holds a barrier
-        const uint32_t count = __builtin_amdgcn_readfirstlane(a.hist[cur]);
-        const uint32_t start = __builtin_amdgcn_readfirstlane(a.offs[cur]);
-        if (count == 0) continue;
-        if (cur == a.nbf) {
-            if (slice == 0) {
-                for (uint32_t j = tid; j < count; j += HESS_TB) hess_nan<AT, C>(a, long(a.perm[start + j]));
-                if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
-            }
-            continue;
-        }
-        const bool pair = count <= uint32_t(HESS_TB / 2);
-        const int stride = pair ? HESS_TB / 2 : HESS_TB;
-        const uint32_t rounds = (count + uint32_t(stride) - 1) / uint32_t(stride);
-        if (slice >= rounds) continue;
-        const int o0 = int(compact3(cur >> 2)) * 8;
-        const int o1 = int(compact3(cur >> 1)) * 8;
-        const int o2 = int(compact3(cur)) * 8;
+    if (cur == a.nbf) {
+        for (uint32_t j = tid; j < count; j += HESS_TB) hess_nan<AT, C>(a, long(a.perm[start + j]));
+        if (tid == 0) atomicAdd(a.nonfinite, (unsigned long long)count);
+        return;
+    }
+    const bool pair = count <= uint32_t(HESS_TB / 2);
+    const int stride = pair ? HESS_TB / 2 : HESS_TB;
+    const int o0 = int(compact3(cur >> 2)) * 8;
+    const int o1 = int(compact3(cur >> 1)) * 8;
+    const int o2 = int(compact3(cur)) * 8;
+    if (fill) {
         // the block's 16-byte slots, global -> LDS, all requested at once
         block_dma<N, CT, C, G, HESS_TB>(static_cast<const CT*>(a.grid), a.n0, a.n1, a.P1, a.pitch2, o0, o1, o2, lds);
         __builtin_amdgcn_s_waitcnt(0);
         lds_barrier();
-        const uint32_t jlane = pair ? uint32_t(tid >> 1) : uint32_t(tid);
-        const int half = pair ? (tid & 1) : 0;
-        for (uint32_t j0 = slice * uint32_t(stride); j0 < count; j0 += uint32_t(stride) * HESS_SLICES) {
-            const uint32_t jj = j0 + jlane;
-            const bool active = jj < count;
-            const uint32_t slot = start + (active ? jj : 0u);
-            const long p = long(a.perm[slot]);
-            const double x[3] = {a.pos_sorted[3 * long(slot)], a.pos_sorted[3 * long(slot) + 1],
-                                 a.pos_sorted[3 * long(slot) + 2]};
-            int cell[3];
-            AT w[3][N], wd[3][N], wdd[3][N];
-            hess_setup<N, AT>(a, x, cell, w, wd, wdd);  // finite by construction of the tile
-            const CT* base = tile + ((cell[0] - o0) * G::R1 + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * C;
-            auto rows = [base](int ia, int ib) { return base + (ia * G::R1 + ib) * G::LROW; };
-            if (pair) {
-                const int ia0 = half * (N / 2);
-                AT w0s[N / 2], wd0s[N / 2], wdd0s[N / 2];
+    }
+    const uint32_t jlane = pair ? uint32_t(tid >> 1) : uint32_t(tid);
+    const int half = pair ? (tid & 1) : 0;
+    for (uint32_t j0 = 0; j0 < count; j0 += uint32_t(stride)) {
+        const uint32_t jj = j0 + jlane;
+        const bool active = jj < count;
+        const uint32_t slot = start + (active ? jj : 0u);
+        const long p = long(a.perm[slot]);
+        const double x[3] = {a.pos_sorted[3 * long(slot)], a.pos_sorted[3 * long(slot) + 1],
+                             a.pos_sorted[3 * long(slot) + 2]};
+        int cell[3];
+        AT w[3][N], wd[3][N], wdd[3][N];
+        hess_setup<N, AT>(a, x, cell, w, wd, wdd);  // finite by construction of the tile
+        const CT* base = tile + ((cell[0] - o0) * G::R1 + (cell[1] - o1)) * G::LROW + (cell[2] - o2) * C;
+        auto rows = [base](int ia, int ib) { return base + (ia * G::R1 + ib) * G::LROW; };
+        if (pair) {
+            const int ia0 = half * (N / 2);
+            AT w0s[N / 2], wd0s[N / 2], wdd0s[N / 2];
 #pragma unroll
-                for (int k = 0; k < N / 2; ++k) {
-                    w0s[k] = half ? w[0][N / 2 + k] : w[0][k];
-                    wd0s[k] = half ? wd[0][N / 2 + k] : wd[0][k];
-                    wdd0s[k] = half ? wdd[0][N / 2 + k] : wdd[0][k];
-                }
-                HessSums<AT, C> mine, other;
-                hess_planes<N, CT, AT, C, N / 2>(w0s, wd0s, wdd0s, w, wd, wdd,
-                                                 [&](int k, int ib) { return rows(ia0 + k, ib); }, mine);
-#pragma unroll
-                for (int m = 0; m < 10; ++m)
-#pragma unroll
-                    for (int c = 0; c < C; ++c) other.s[m][c] = __shfl_xor(mine.s[m][c], 1, 64);
-                if (active && half == 0) hess_store<AT, C>(a, p, mine, other);
-            } else {
-                HessSums<AT, C> lo, hi;
-                hess_planes<N, CT, AT, C, N / 2>(w[0], wd[0], wdd[0], w, wd, wdd, rows, lo);
-                hess_planes<N, CT, AT, C, N / 2>(w[0] + N / 2, wd[0] + N / 2, wdd[0] + N / 2, w, wd, wdd,
-                                                 [&](int k, int ib) { return rows(N / 2 + k, ib); }, hi);
-                if (active) hess_store<AT, C>(a, p, lo, hi);
+            for (int k = 0; k < N / 2; ++k) {
+                w0s[k] = half ? w[0][N / 2 + k] : w[0][k];
+                wd0s[k] = half ? wd[0][N / 2 + k] : wd[0][k];
+                wdd0s[k] = half ? wdd[0][N / 2 + k] : wdd[0][k];
             }
+            HessSums<AT, C> mine, other;
+            hess_planes<N, CT, AT, C, N / 2>(w0s, wd0s, wdd0s, w, wd, wdd,
+                                             [&](int k, int ib) { return rows(ia0 + k, ib); }, mine);
+#pragma unroll
+            for (int m = 0; m < 10; ++m)
+#pragma unroll
+                for (int c = 0; c < C; ++c) other.s[m][c] = __shfl_xor(mine.s[m][c], 1, 64);
+            if (active && half == 0) hess_store<AT, C>(a, p, mine, other);
+        } else {
+            HessSums<AT, C> lo, hi;
+            hess_planes<N, CT, AT, C, N / 2>(w[0], wd[0], wdd[0], w, wd, wdd, rows, lo);
+            hess_planes<N, CT, AT, C, N / 2>(w[0] + N / 2, wd[0] + N / 2, wdd[0] + N / 2, w, wd, wdd,
+                                             [&](int k, int ib) { return rows(N / 2 + k, ib); }, hi);
+            if (active) hess_store<AT, C>(a, p, lo, hi);
         }
-        lds_barrier();
+    }
+}
+
+// LDS-tiled variant: persistent one-wave workgroups over the work items (the
+// non-empty Morton tiles of 8^3 cells cut into pieces of at most HESS_ROUNDS
+// rounds, so that a crowded tile, a dense cluster of particles, is shared by
+// several CUs).  As in the tiled gather, the items are split into one range per
+// XCD; a workgroup takes the items of its home range (blockIdx % ITEM_RANGES:
+// workgroups are dealt to the XCDs in turn) ITEM_TAKE at a time, then those of
+// the other ranges, and consecutive items of one tile reuse its block in LDS.
+template <int N, typename CT, int C>
+__global__ __launch_bounds__(HESS_TB) void k_gather_hess_tiled(HessArgs a) {
+    using G = TileGeom<N, CT, C, 8, false>;   // rows packed densely (hess_planes reads them)
+    static_assert(sizeof(CT) != 2 || bf16_rows_fit<N, C, 8, G::LROW>(), "BF16 row reads would leave the LDS row");
+    __shared__ u32x4 lds[G::SLOTS];
+    // wave-uniform values steer every loop that holds a barrier
+    const uint32_t W = __builtin_amdgcn_readfirstlane(a.ctl[0]);
+    const uint32_t home = uint32_t(blockIdx.x) % ITEM_RANGES;
+    uint32_t prev = 0xffffffffu;  // tile whose block the LDS holds
+    for (uint32_t r = 0; r < ITEM_RANGES; ++r) {
+        const uint32_t x = (home + r) % ITEM_RANGES;
+        const uint32_t lo = item_range_begin(W, x);
+        const uint32_t hi = item_range_begin(W, x + 1);
+        uint32_t i = item_take_finish<HESS_TB>(item_take_issue(a.ctl, x), nullptr);
+        while (lo + i < hi) {
+            const uint32_t m = min(ITEM_TAKE, hi - lo - i);
+            uint32_t next = 0;
+            for (uint32_t k = 0; k < m; ++k) {
+                const u32x4 it = a.items[lo + i + k];
+                const uint32_t cur = __builtin_amdgcn_readfirstlane(it.x);
+                const uint32_t start = __builtin_amdgcn_readfirstlane(it.y);
+                const uint32_t count = __builtin_amdgcn_readfirstlane(it.z);
+                if (k + 1 == m) next = item_take_issue(a.ctl, x);
+                hess_piece<N, CT, C, G>(a, cur, start, count, lds, cur != prev);
+                if (cur != a.nbf) prev = cur;
+                lds_barrier();  // every LDS read done before a later piece refills it
+            }
+            i = item_take_finish<HESS_TB>(next, nullptr);
+        }
     }
 }
 
@@ -445,14 +464,29 @@ bool hess_tiled_ok(int N, int C) {
     return C == 1 ? ok(TileGeom<6, CT, 1, 8, false>{}) : ok(TileGeom<6, CT, 3, 8, false>{});
 }
 
+// Persistent launch: as many workgroups as stay resident (the kernel's
+// occupancy, asked once per instance) on every CU.
+template <int N, typename CT, int C>
+void launch_hess_tiled(int num_cus, hipStream_t s, const HessArgs& a) {
+    auto k = k_gather_hess_tiled<N, CT, C>;
+    static unsigned per_cu = 0;
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k, HESS_TB, 0) != hipSuccess || v < 1) v = 1;
+        per_cu = unsigned(v);
+    });
+    hipLaunchKernelGGL(k, dim3(per_cu * unsigned(std::max(num_cus, 1))), dim3(HESS_TB), 0, s, a);
+}
+
 template <typename CT>
-void launch_hess_tiled_ct(int N, int C, unsigned nb, hipStream_t s, const HessArgs& a) {
+void launch_hess_tiled_ct(int N, int C, int num_cus, hipStream_t s, const HessArgs& a) {
     if (N == 4) {
-        if (C == 1) hipLaunchKernelGGL((k_gather_hess_tiled<4, CT, 1>), dim3(nb), dim3(HESS_TB), 0, s, a);
-        else hipLaunchKernelGGL((k_gather_hess_tiled<4, CT, 3>), dim3(nb), dim3(HESS_TB), 0, s, a);
+        if (C == 1) launch_hess_tiled<4, CT, 1>(num_cus, s, a);
+        else launch_hess_tiled<4, CT, 3>(num_cus, s, a);
     } else {
-        if (C == 1) hipLaunchKernelGGL((k_gather_hess_tiled<6, CT, 1>), dim3(nb), dim3(HESS_TB), 0, s, a);
-        else hipLaunchKernelGGL((k_gather_hess_tiled<6, CT, 3>), dim3(nb), dim3(HESS_TB), 0, s, a);
+        if (C == 1) launch_hess_tiled<6, CT, 1>(num_cus, s, a);
+        else launch_hess_tiled<6, CT, 3>(num_cus, s, a);
     }
 }
 
@@ -479,8 +513,21 @@ bsi_status hessian_run(bsi_field* f, const double* pos, int64_t P, void* u, void
     const int nmax = std::max(f->n[0], std::max(f->n[1], f->n[2]));
     const int tile = std::max(8, (nmax + 255) / 256);
     const BinLayout l = bin_layout(f, long(P), tile);
+    const int coef = f->desc.coef;
+    const bool tiled = tile == 8 && (coef == BSI_F64   ? hess_tiled_ok<double>(f->N, f->C)
+                                     : coef == BSI_F32 ? hess_tiled_ok<float>(f->N, f->C)
+                                                       : hess_tiled_ok<uint16_t>(f->N, f->C));
+    // work items of the tiled kernel after the binning's arrays: at most one
+    // per non-empty tile plus one per `chunk` particles, then the control
+    // words and the per-group item sums
+    const uint32_t chunk = uint32_t(HESS_TB) * HESS_ROUNDS;
+    const size_t nb = bin_bucket_count(f, tile) + 1;
+    const size_t o_items = (l.bytes + 15) / 16 * 16;
+    const size_t o_ctl = o_items + (nb + size_t(P) / chunk + 1) * 16;
+    const size_t o_sums = o_ctl + ITEM_CTL_WORDS * sizeof(uint32_t);
+    const size_t bytes = tiled ? o_sums + (nb + SCAN_CHUNK - 1) / SCAN_CHUNK * sizeof(uint32_t) : l.bytes;
     void* ws = nullptr;
-    BSI_TRY(get_workspace(f->ctx->eval_ws, s, l.bytes, &ws));
+    BSI_TRY(get_workspace(f->ctx->eval_ws, s, bytes, &ws));
     char* w = static_cast<char*>(ws);
     uint32_t* perm = reinterpret_cast<uint32_t*>(w + l.perm);
     double* pos_sorted = reinterpret_cast<double*>(w + l.pos);
@@ -506,17 +553,31 @@ bsi_status hessian_run(bsi_field* f, const double* pos, int64_t P, void* u, void
     a.grad = grad;
     a.hess = hess;
     a.nonfinite = f->counters;
-    const int coef = f->desc.coef;
-    const bool tiled = tile == 8 && (coef == BSI_F64   ? hess_tiled_ok<double>(f->N, f->C)
-                                     : coef == BSI_F32 ? hess_tiled_ok<float>(f->N, f->C)
-                                                       : hess_tiled_ok<uint16_t>(f->N, f->C));
+    a.items = nullptr;
+    a.ctl = nullptr;
+    if (tiled) {
+        StageTimer tm(f->ctx, "hess_items", s);
+        const uint32_t* hist = a.hist;
+        const unsigned ng = unsigned((nb + SCAN_CHUNK - 1) / SCAN_CHUNK);
+        uint32_t* sums = reinterpret_cast<uint32_t*>(w + o_sums);
+        u32x4* items = reinterpret_cast<u32x4*>(w + o_items);
+        uint32_t* ctl = reinterpret_cast<uint32_t*>(w + o_ctl);
+        hipLaunchKernelGGL(k_item_sums, dim3(ng), dim3(SCAN_BLOCK), 0, s, hist, long(nb), chunk, sums);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, s, sums, int(ng));
+        hipLaunchKernelGGL(k_items, dim3(ng), dim3(SCAN_BLOCK), 0, s, hist, a.offs, long(nb), chunk, sums, items,
+                           ctl);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, ctl + ITEM_CTL_STRIDE,
+                           long(ITEM_CTL_STRIDE * ITEM_RANGES), 0u);
+        a.items = items;
+        a.ctl = ctl;
+    }
     {
         StageTimer tm(f->ctx, "gather_hess", s);
         if (tiled) {
-            const unsigned nb = unsigned((size_t(a.nbf) + 1 + HESS_TPG - 1) / HESS_TPG) * HESS_SLICES;
-            if (coef == BSI_F64) launch_hess_tiled_ct<double>(f->N, f->C, nb, s, a);
-            else if (coef == BSI_F32) launch_hess_tiled_ct<float>(f->N, f->C, nb, s, a);
-            else launch_hess_tiled_ct<uint16_t>(f->N, f->C, nb, s, a);
+            const int cus = f->ctx->num_cus;
+            if (coef == BSI_F64) launch_hess_tiled_ct<double>(f->N, f->C, cus, s, a);
+            else if (coef == BSI_F32) launch_hess_tiled_ct<float>(f->N, f->C, cus, s, a);
+            else launch_hess_tiled_ct<uint16_t>(f->N, f->C, cus, s, a);
         } else {
             const unsigned nb = unsigned((P + HESS_B - 1) / HESS_B);
             if (coef == BSI_F64) launch_hess_ct<double>(f->N, f->C, nb, s, a);
