@@ -940,7 +940,8 @@ def form_batch(args):
     ctx.close()
     config = {"workload": "64 divergence-free Kolmogorov fields, n uniform over {64,128,192,256}, order "
                           "uniform over {4,6}, FP32 grids, 10^U(3,6) uniform particles each; step = one "
-                          "replay of the captured graph (binning + one persistent gather launch)",
+                          "replay of the captured graph (binning, then per (order, components) class a persistent tile "
+                          "gather and a direct gather launch)",
               "fields": len(specs), "particles": Ptot, "tiled_items": n_tiled,
               "direct_items": len(specs) - n_tiled, "tuning_runs": len(tuned), "parallelism": "single GPU"}
     STEP_PERCENTILES.clear()
