@@ -1015,14 +1015,22 @@ def serve_run(args, nreq):
         """Submit requests start..start+nreq-1: Poisson arrivals at `rate`
         requests/s, or closed loop with `closed` outstanding requests."""
         tickets = []
+        collected = set()
+
+        def collect(t):
+            # a ticket's results are collected once (a second wait is an error)
+            if t not in collected:
+                sv.wait(t)
+                collected.add(t)
+
         rng = np.random.default_rng(start)
         t_next = time.perf_counter()
         for i in range(nreq):
             j = len(tickets)
             if j >= nbuf:                      # output buffer reuse
-                sv.wait(tickets[j - nbuf])
+                collect(tickets[j - nbuf])
             if closed is not None and j >= closed:
-                sv.wait(tickets[j - closed])
+                collect(tickets[j - closed])
             if rate is not None:
                 t_next += rng.exponential(1.0 / rate)
                 while time.perf_counter() < t_next:
@@ -1031,7 +1039,7 @@ def serve_run(args, nreq):
             u, g = outs[j % nbuf]
             tickets.append(sv.submit(fid, pos, u[:Pr], g[:Pr]))
         for t in tickets:
-            sv.wait(t)
+            collect(t)
         return sv.stats()
 
     eprint("warm-up ...")
