@@ -272,7 +272,7 @@ bsi_status bsi_debug_bins(bsi_field* field, const double* pos_dev, int64_t P, in
  * (synchronises the field's last stream). */
 bsi_status bsi_field_stats(bsi_field* field, int64_t* nonfinite_positions);
 
-/* ---- batching: many fields in one persistent launch ----------------------- */
+/* ---- batching: many fields in one graph of a few launches ---------------- */
 
 /* One evaluation inside a batch: the arguments of bsi_eval for one field. */
 typedef struct bsi_eval_item {
@@ -287,11 +287,12 @@ typedef struct bsi_batch bsi_batch;
 
 /* (Items must be B-spline fields of orders 4 and 6; BSI_E_UNSUPPORTED otherwise.)
  * Plan the evaluation of `count` items (1..65535) as one unit of work: every
- * item's particles are binned by the Morton tile of its own sort granularity,
- * and one persistent gather kernel walks a shared work list -- the non-empty
- * tiles of the items gathered from LDS tiles (8^3 cells) and groups of
- * 64 binned particles of the items gathered one lane per particle -- so that
- * large and small items share the GPU without a launch per item.  cfgs (count
+ * item's particles are binned by the Morton tile of its own sort granularity
+ * (one set of binning launches for all items), and per (order, components)
+ * class present one persistent kernel walks the class's non-empty tiles of the
+ * items gathered from LDS tiles (8^3 cells) and one kernel takes the class's
+ * groups of 64 binned particles of the items gathered one lane per particle,
+ * so that large and small items share the GPU without a launch per item.  cfgs (count
  * entries) gives each item's configuration, or NULL for the tuned ones
  * (bsi_ctx_lookup_config); a tiled configuration is run with 8^3-cell tiles
  * (one lane per particle if the class has no such tile).  Results are bitwise those of
