@@ -103,8 +103,9 @@ typedef struct bsi_eval_config {
                             8, 12, 16 whose block is at most 64 KB of LDS and whose origin is
                             16-byte aligned); otherwise, and for 1, one thread per particle
                             reading the grid directly */
-    int32_t tiles_per_group; /* persistent batch gather: consecutive Morton tiles of one item
-                                walked by one workgroup (0 = 4); unused by single-field evaluation */
+    int32_t tiles_per_group; /* read by no kernel now (the tiled gather takes work items, the
+                                batch's tile kernels one tile at a time); kept so that tuning
+                                records and callers' structs keep their layout; any value */
     int32_t tile_block;      /* threads per workgroup of the tiled gather with 8^3-cell tiles:
                                 0 or 64 = one wavefront per tile, 256 = four wavefronts share a
                                 tile (dense tiles); other tile sizes have a fixed block */
