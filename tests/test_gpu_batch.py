@@ -72,8 +72,8 @@ SPECS = [
     (32, 3, 6, 2500, (12, 0)),
     # every (order, components) class with tiled and direct items: each class
     # has a tile kernel and a direct kernel of its own
-    (40, 1, 4, 9000, (8, 0)),
-    (28, 1, 6, 6000, (8, 0)),
+    (48, 1, 4, 9000, (8, 0)),
+    (36, 1, 6, 6000, (8, 0)),
     (24, 1, 4, 5000, (8, 1)),
 ]
 
