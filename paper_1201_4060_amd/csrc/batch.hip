@@ -261,7 +261,7 @@ struct bsi_batch {
     bool grad = true;
     int nitems = 0;                      // items with P > 0
     uint64_t Ptot = 0, Btot = 0;
-    uint32_t npblocks = 0, nbblocks = 0, ndirect = 0;
+    uint32_t nbblocks = 0;
     uint32_t dbeg[NCLASS] = {}, dend[NCLASS] = {};  // direct units of each class
     uint32_t tbound[NCLASS] = {};   // buckets of the class's tiled items (bound on its tiles)
     unsigned tgrid[NCLASS] = {};    // persistent tile grid of each class
@@ -499,9 +499,7 @@ bsi_status bsi_batch_create(bsi_ctx* ctx, const bsi_eval_item* items, int32_t co
     b->nitems = int(hi.size());
     b->Ptot = pbase;
     b->Btot = Btot;
-    b->npblocks = uint32_t(pblock.size());
     b->nbblocks = uint32_t(bblock.size());
-    b->ndirect = uint32_t(dunit.size());
     if (b->nitems == 0) {
         *out = b;
         return BSI_OK;
