@@ -91,6 +91,18 @@ def test_hessian_nonfinite_empty_and_no_grad(ctx):
         assert rel_err(h[:-2], wh).max() < TOL_F64
         u0, g0, h0 = f.eval_hessian(torch.empty((0, 3), dtype=torch.float64, device="cuda"))
         assert h0.shape == (0, C, 6)
+        # more positions without a cell than one work item holds (the bucket
+        # of non-finite positions is cut into several items, each counted)
+        bad = np.full((700, 3), np.nan)
+        bad[::3, 1] = np.inf
+        mixed = np.concatenate([bad, synth.uniform_positions(300, seed=62)])
+        before = f.nonfinite_count()
+        u, g, h = f.eval_hessian(dev(mixed))
+        u, g, h = host(u), host(g), host(h)
+        assert f.nonfinite_count() - before == 700
+        assert np.isnan(u[:700]).all() and np.isnan(g[:700]).all() and np.isnan(h[:700]).all()
+        _, _, wh = evaluate_hessian(grid, mixed[700:], N)
+        assert rel_err(h[700:], wh).max() < TOL_F64
 
 
 @pytest.mark.parametrize("N", [4, 6])
